@@ -1,0 +1,229 @@
+"""Pins for the CPU oracle: brute force, closed forms, invariants, statistics.
+
+Each check is independent of the oracle's own code path (pure-Python sorts and
+sums, the ``statistics`` module, closed-form S/N, Gaussian tail probabilities),
+so that a dropped term, a wrong sign or index, or a transposed operand in the
+oracle fails at least one of them.
+"""
+import math
+import statistics
+
+import numpy as np
+import pytest
+from scipy.stats import norm
+
+import oracle
+import synth
+
+K = 1.482602218505602
+
+
+def brute_stats(x, L, S):
+    """Lower median and MAD of each trailing window by sorting Python lists."""
+    n = len(x)
+    ms, mads = [], []
+    for k in range((n + S - 1) // S):
+        e = min(k * S + S, n)
+        w = sorted(x[max(0, e - L):e])
+        r = (len(w) - 1) // 2
+        m = w[r]
+        d = sorted(abs(v - m) for v in w)[r]
+        ms.append(m)
+        mads.append(d)
+    return ms, mads
+
+
+def brute_search_row(x, dm, max_width, L, theta, S):
+    """Whole search for one row with explicit loops only."""
+    ms, mads = brute_stats(x, L, S)
+    n = len(x)
+    r = [x[t] - ms[t // S] for t in range(n)]
+    th = float(np.float32(theta))
+    out = []
+    w = 1
+    while w <= max_width:
+        vals = []
+        for i in range(n - w + 1):
+            s = sum(r[i:i + w])
+            mad = mads[(i + w // 2) // S]
+            if mad == 0:
+                vals.append(None)
+                continue
+            snr = s / ((K * mad) * math.sqrt(w))
+            vals.append(snr if snr > th else None)
+        i = 0
+        while i < len(vals):
+            if vals[i] is None:
+                i += 1
+                continue
+            j, best, bi = i, vals[i], i
+            while j < len(vals) and vals[j] is not None:
+                if vals[j] > best:
+                    best, bi = vals[j], j
+                j += 1
+            out.append((bi, dm, w, float(np.float32(best))))
+            i = j
+        w *= 2
+    return sorted(out, key=lambda c: (c[1], c[2], c[0]))
+
+
+def as_tuples(c):
+    return [(int(a), int(b), int(w), float(s)) for a, b, w, s in zip(c["sample"], c["dm_idx"], c["width"], c["snr"])]
+
+
+@pytest.mark.parametrize("n,L,S,seed", [(1, 5, 4, 0), (7, 3, 4, 1), (40, 9, 4, 2), (64, 64, 8, 3), (93, 17, 8, 4),
+                                        (130, 1000, 16, 5), (257, 40, 64, 6), (300, 128, 64, 7)])
+def test_median_mad_brute_force(n, L, S, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.integers(-50, 50, size=n)
+    # heavy ties in one half, spread values in the other
+    x[: n // 2] = rng.integers(0, 3, size=n // 2)
+    m, mad = oracle.block_median_mad(x.astype(np.float32), L, S)
+    bm, bmad = brute_stats(x.tolist(), L, S)
+    assert m.tolist() == bm
+    assert mad.tolist() == bmad
+
+
+def test_median_is_statistics_median_low_when_window_covers_row():
+    # Special case L >= N: every window is a prefix; the last one is the row.
+    rng = np.random.default_rng(11)
+    for n in (63, 64, 100, 129):
+        x = rng.integers(-1000, 1000, size=n)
+        m, mad = oracle.block_median_mad(x, 10 * n, 64)
+        ml = statistics.median_low(x.tolist())
+        assert m[-1] == ml
+        assert mad[-1] == statistics.median_low([abs(v - ml) for v in x.tolist()])
+        # first block: prefix of length min(64, n)
+        p = x[: min(64, n)].tolist()
+        assert m[0] == statistics.median_low(p)
+
+
+def test_boxcar_direct_sums():
+    rng = np.random.default_rng(3)
+    r = rng.integers(-100, 100, size=50)
+    for w in (1, 2, 4, 8, 16, 32, 64):
+        got = oracle.boxcar(r, w)
+        want = [sum(r[i:i + w].tolist()) for i in range(len(r) - w + 1)] if w <= len(r) else []
+        assert got.tolist() == want
+        if w <= len(r):
+            assert np.array_equal(got, np.convolve(r, np.ones(w, dtype=np.int64), "valid"))
+
+
+@pytest.mark.parametrize("seed,n,L,S,maxw,theta", [(0, 200, 50, 8, 16, 1.5), (1, 333, 64, 16, 32, 1.2),
+                                                    (2, 129, 500, 64, 64, 1.0), (3, 90, 7, 4, 8, 2.0)])
+def test_search_row_brute_force(seed, n, L, S, maxw, theta):
+    rng = np.random.default_rng(seed)
+    x = rng.integers(0, 40, size=n)
+    x[n // 3: n // 3 + 5] += 60  # a pulse so that wide widths fire too
+    got = as_tuples(oracle.search_row(x, 5, maxw, L, theta, S))
+    want = brute_search_row(x.tolist(), 5, maxw, L, theta, S)
+    assert got == want
+    assert len(got) > 0
+
+
+def test_peaks_first_argmax_and_run_breaks():
+    above = np.array([0, 1, 1, 1, 0, 1, 0, 0, 1, 1], dtype=bool)
+    snr = np.array([9, 2, 5, 5, 9, 3, 9, 9, 7, 8], dtype=float)
+    assert oracle.peaks(above, snr) == [(2, 5.0), (5, 3.0), (9, 8.0)]
+    assert oracle.peaks(np.zeros(4, bool), snr[:4]) == []
+    assert oracle.peaks(np.ones(3, bool), np.array([1.0, 1.0, 1.0])) == [(0, 1.0)]
+
+
+def test_mad_zero_is_never_above():
+    # Constant data: r == 0 exactly, MAD == 0, hence no candidates at all.
+    x = np.full((3, 777), 12345.0, dtype=np.float32)
+    c, m, mad = oracle.search(x, 64, 100, 0.5, with_stats=True)
+    assert c.size == 0
+    assert (m == 12345).all() and (mad == 0).all()
+    assert (oracle.residual(x[0], m[0]) == 0).all()
+    # MAD == 0 in one block breaks a run even if S is huge there
+    snr, above = oracle.snr_and_above(np.array([100, 100, 100]), np.array([5, 0, 5]), 1, 1.0, stride=1)
+    assert above.tolist() == [True, False, True]
+
+
+def periodic_pulse_row(n, base, s, t0, w, amp):
+    """Period-7 pattern (-2,-1,-1,0,1,1,2)*s with a zero run of 4w around a width-w pulse."""
+    pat = np.array([-2, -1, -1, 0, 1, 1, 2]) * s
+    x = base + pat[np.arange(n) % 7]
+    x[t0 - 2 * w: t0 + 3 * w] = base
+    x[t0: t0 + w] += amp
+    return x
+
+
+@pytest.mark.parametrize("w,expect", [(1, 6.744898), (4, 13.489795), (32, 38.154902)])
+def test_snr_closed_form(w, expect):
+    # m = base, MAD = s exactly, so the best candidate is at (t0, w) with snr = A sqrt(w) / (K s).
+    base, s, amp, n, L = 32768, 100, 1000, 8192, 4096
+    t0 = 6001
+    x = periodic_pulse_row(n, base, s, t0, w, amp)
+    c, m, mad = oracle.search(x[None, :].astype(np.float32), 64, L, 6.0, with_stats=True)
+    assert (m == base).all()
+    assert (mad == s).all()
+    closed = amp * math.sqrt(w) / (K * s)
+    assert abs(closed - expect) < 5e-6
+    best = c[np.argmax(c["snr"])]
+    assert (int(best["sample"]), int(best["width"])) == (t0, w)
+    assert best["snr"] == np.float32(closed)
+    # nothing fires away from the pulse: |S_w| <= 3s on the periodic pattern
+    assert ((c["sample"] >= t0 - 64) & (c["sample"] < t0 + w + 64)).all()
+
+
+def test_translation_invariance_bit_exact():
+    b = synth.Block(ndm=3, nsamp=6000, max_width=64, baseline_len=1000, seed=77, n_pulses=3,
+                    pulse_snr=(8, 20))
+    x = synth.generate(b)
+    c0 = oracle.search(x, 64, 1000, 5.0)
+    c1 = oracle.search(x + np.float32(-20000), 64, 1000, 5.0)
+    assert c0.size > 0
+    assert np.array_equal(c0, c1)
+
+
+def test_scale_invariance():
+    b = synth.Block(ndm=2, nsamp=5000, max_width=32, baseline_len=700, seed=78, n_pulses=2,
+                    pulse_snr=(8, 20))
+    x = oracle.to_int(synth.generate(b)) - 32768
+    c0 = oracle.search(x, 32, 700, 5.0)
+    c3 = oracle.search(3 * x, 32, 700, 5.0)
+    assert np.array_equal(c0[["sample", "dm_idx", "width"]], c3[["sample", "dm_idx", "width"]])
+    np.testing.assert_allclose(c0["snr"], c3["snr"], rtol=1e-6)
+
+
+@pytest.mark.slow
+def test_noise_only_false_alarms_gaussian_tail():
+    # Drift-free integer Gaussian noise, width 1: the number of above positions
+    # (after the first L samples, whose windows are clipped) follows the
+    # Gaussian tail count N_eff * Q(theta) to within Poisson scatter.
+    b = synth.Block(ndm=6, nsamp=1 << 19, max_width=1, baseline_len=16384, seed=4242, drift_amp_sigma=0.0)
+    x = synth.generate(b)
+    for th in (4.0, 4.5):
+        tot, neff = 0, 0
+        for r in range(b.ndm):
+            m, mad = oracle.block_median_mad(x[r], b.baseline_len)
+            sw = oracle.boxcar(oracle.residual(x[r], m), 1)
+            _, above = oracle.snr_and_above(sw, mad, 1, th)
+            tot += int(above[b.baseline_len:].sum())
+            neff += above.size - b.baseline_len
+        lam = neff * norm.sf(th)
+        z = (tot - lam) / math.sqrt(lam)
+        assert abs(z) < 4.0, (th, tot, lam, z)
+
+
+def test_stream_equals_concatenation_and_batch_is_per_item():
+    b = synth.Block(ndm=2, nsamp=4096, max_width=16, baseline_len=500, seed=5, n_pulses=2, pulse_snr=(8, 12))
+    x = synth.generate(b)
+    whole = oracle.search(x, 16, 500, 5.0)
+    assert np.array_equal(oracle.search_stream([x[:, :1024], x[:, 1024:3072], x[:, 3072:]], 16, 500, 5.0), whole)
+    res = oracle.search_batch([(x, 16, 500, 5.0), (x[:1, :2000], 8, 300, 4.0)])
+    assert np.array_equal(res[0], whole)
+    assert np.array_equal(res[1], oracle.search(x[:1, :2000], 8, 300, 4.0))
+
+
+def test_widths_and_edges():
+    assert oracle.widths(1) == [1]
+    assert oracle.widths(64) == [1, 2, 4, 8, 16, 32, 64]
+    # widths longer than the row give no positions
+    x = np.arange(10, dtype=np.float32)
+    c = oracle.search(x[None, :], 64, 5, 0.1)
+    assert (c["width"] <= 10).all()
+    # a single-sample row: MAD = 0, nothing
+    assert oracle.search(np.ones((1, 1), np.float32), 4, 4, 0.1).size == 0
