@@ -1,0 +1,161 @@
+/*
+ * sps.h - C interface of libsps, the MI355X (gfx950) single-pulse search.
+ *
+ * The library runs, on one GPU, the per-DM-trial part of a single-pulse
+ * search over a block of dedispersed time series: baseline removal,
+ * normalisation, matched filtering with a bank of boxcars, and peak
+ * detection above an S/N threshold, producing candidates (time, DM trial,
+ * filter width, peak S/N). These are the four stages of the DM-trial loop in
+ * Heimdall++ (Section II-B, "Pipeline Stages in Heimdall"; Algorithm 1, the
+ * parallel candidate search). The paper names the stages without formulas;
+ * the exact arithmetic implemented here is:
+ *
+ *   x_t       integer value of sample t of a row (inputs are integer-valued)
+ *   block k   samples [kS, min(kS+S, N)), S = 64; e_k = min(kS+S, N)
+ *   W_k       trailing window x[max(0, e_k - L) : e_k]
+ *   m_k       lower median of W_k (element of rank floor((n-1)/2))
+ *   MAD_k     lower median of |W_k - m_k|
+ *   r_t       x_t - m_{floor(t/S)}
+ *   S_w(i)    sum of r over [i, i+w), w = 1, 2, 4, ..., max_width, 0 <= i <= N-w
+ *   snr       S_w(i) / ((K * MAD_{k*}) * sqrt(w)) in IEEE double, K = 1/Phi^-1(3/4),
+ *             k* = floor((i + floor(w/2)) / S); positions with MAD_{k*} = 0 are never above
+ *   above     snr > (double)snr_thresh
+ *   candidate one per maximal run of above positions of a (row, width), at the
+ *             run's first arg-max: {sample = i, dm_idx = row, width = w, snr = (float)snr}
+ *
+ * Conventions for every entry point:
+ *   - Device pointers ("d_" prefix) are HIP device memory owned by the caller
+ *     (e.g. torch tensors); they must stay valid until the stream work ends.
+ *   - Calls that take a hipStream_t are asynchronous and stream-ordered; they
+ *     never synchronise the device. Argument errors are reported synchronously
+ *     by the return code and nothing is enqueued.
+ *   - Return codes: SPS_OK (0) or a negative SPS_ERR_* value; sps_last_error()
+ *     returns the last code of the calling thread, sps_error_string() a text.
+ *   - A plan may be used by one stream at a time (it owns scratch memory).
+ *   - Input domain: FP32 samples with integer values, |x| < 2^24, and every
+ *     boxcar sum |S_w(i)| < 2^31. Outside this domain results are unspecified
+ *     (no out-of-bounds access ever results).
+ */
+#ifndef SPS_H
+#define SPS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define SPS_OK 0
+#define SPS_ERR_INVALID_ARG (-1) /* bad argument: nothing was enqueued */
+#define SPS_ERR_OOM (-2)         /* device memory allocation failed */
+#define SPS_ERR_HIP (-3)         /* a HIP runtime call failed (e.g. launch) */
+#define SPS_ERR_OVERFLOW (-4)    /* candidate count exceeded the capacity (reported by callers) */
+#define SPS_ERR_DOMAIN (-5)      /* input outside the supported domain */
+
+/* One candidate, 16 bytes. sample: first sample of the boxcar window, counted
+ * from the first sample of the call's input (negative in streaming mode when
+ * the run began in the carried history); dm_idx: row (plus the batch item's
+ * row offset); width: boxcar width; snr: peak S/N rounded to FP32. */
+typedef struct {
+    int32_t sample;
+    uint32_t dm_idx;
+    uint32_t width;
+    float snr;
+} sps_cand;
+
+typedef struct sps_plan sps_plan;
+
+/* Limits of this build. */
+#define SPS_BLOCK_STRIDE 64          /* S: samples per baseline block */
+#define SPS_MAX_WIDTH_LIMIT 4096     /* largest boxcar width */
+#define SPS_MAX_BASELINE_LEN 65535   /* largest baseline window L */
+
+/*
+ * Create a plan for blocks of ndm rows x nsamp samples (row-major FP32,
+ * row stride nsamp): boxcar widths 1, 2, 4, ..., max_width; baseline window
+ * of baseline_len samples; threshold snr_thresh (in units of the robust sigma).
+ * Requirements: ndm >= 1; 1 <= nsamp < 2^31; max_width a power of two in
+ * [1, SPS_MAX_WIDTH_LIMIT]; 1 <= baseline_len <= SPS_MAX_BASELINE_LEN;
+ * snr_thresh finite and > 0. Allocates the plan's device scratch
+ * (about 8 bytes per 64 samples plus small tables) on the current device.
+ * Returns NULL on error (sps_last_error() tells which).
+ * Stages: Section II-B (all four per-trial stages); Algorithm 1.
+ */
+sps_plan* sps_plan_create(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baseline_len,
+                          float snr_thresh);
+
+/* Free a plan and its device scratch. NULL-safe. Synchronises the device
+ * first so that no enqueued work still uses the scratch. */
+void sps_plan_destroy(sps_plan* plan);
+
+/*
+ * Search d_series (device, FP32 [ndm][nsamp]) on `stream`.
+ * Candidates go to d_cands (device, capacity given by SPS_ATTR_MAX_CANDS,
+ * default 2^24 records); *d_ncand (device uint32) is zeroed in-stream and
+ * holds the TRUE number of candidates after the work completes. If it exceeds
+ * the capacity, only `capacity` records were written (which ones is
+ * unspecified) and the caller should retry with a larger buffer. Candidate
+ * order is unspecified: compare sorted by (dm_idx, width, sample).
+ * Stages: Section II-B; Algorithm 1, the per-trial kernels of the parallel
+ * candidate search, here fused and launched over all rows at once.
+ */
+int sps_search(sps_plan* plan, const float* d_series, hipStream_t stream, sps_cand* d_cands,
+               uint32_t* d_ncand);
+
+/*
+ * Baseline-removal and normalisation stages only: write m_k and MAD_k of
+ * every block of every row to d_median and d_mad (device int32
+ * [ndm][ceil(nsamp/64)], row stride ceil(nsamp/64)). Section II-B,
+ * "Baseline Removal and Normalization".
+ */
+int sps_block_stats(sps_plan* plan, const float* d_series, hipStream_t stream, int32_t* d_median,
+                    int32_t* d_mad);
+
+/*
+ * The same search as sps_search, executed as plain per-stage kernels with
+ * every intermediate (medians, residuals, prefix sums, boxcar outputs,
+ * per-position S/N decisions) materialised in device memory, one launch per
+ * stage and width, as the staged DM-trial loop of Section II-B runs. Results
+ * equal sps_search's exactly. Allocates its larger scratch (about
+ * 12 bytes per sample) on first use and keeps it with the plan.
+ */
+int sps_search_plain(sps_plan* plan, const float* d_series, hipStream_t stream, sps_cand* d_cands,
+                     uint32_t* d_ncand);
+
+/* Plan attributes (sps_plan_set / sps_plan_get). */
+#define SPS_ATTR_MAX_CANDS 1      /* capacity of d_cands in records (default 1<<24) */
+#define SPS_ATTR_STATS_SEG 2      /* blocks per baseline chain segment (tuning; 0 = auto) */
+#define SPS_ATTR_DETECT_SEG 3     /* samples per detection segment, multiple of 1024 (0 = auto) */
+#define SPS_ATTR_HIST_BINS 4      /* fine histogram span in values: 4096 or 16384 (tuning) */
+#define SPS_ATTR_TIMING 5         /* 1: record HIP events around every kernel of a search */
+#define SPS_ATTR_NBLOCKS 16       /* read-only: ceil(nsamp / 64) */
+#define SPS_ATTR_NWIDTHS 17       /* read-only: number of boxcar widths */
+
+/* Tuning attributes never change results, only speed. Returns SPS_OK or
+ * SPS_ERR_INVALID_ARG (unknown attribute, value out of range, read-only). */
+int sps_plan_set(sps_plan* plan, int attr, int64_t value);
+int sps_plan_get(const sps_plan* plan, int attr, int64_t* value);
+
+/*
+ * Kernel timing (tracing). With SPS_ATTR_TIMING = 1 every search records HIP
+ * events on its stream around each kernel. sps_timing_read waits for the
+ * recorded events, writes the summed milliseconds per stage since the last
+ * read to ms_out[SPS_NSTAGES] and the number of searches to *nsearch, and
+ * resets the sums. Stages: 0 baseline/normalisation kernel, 1 fused
+ * filter/detect kernel, 2 fix-up and counter reset, 3 plain per-stage path
+ * (whole search). Host-synchronous.
+ */
+#define SPS_NSTAGES 4
+int sps_timing_read(sps_plan* plan, double* ms_out, int64_t* nsearch);
+
+/* Last error code of the calling thread, and a static text for a code. */
+int sps_last_error(void);
+const char* sps_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPS_H */

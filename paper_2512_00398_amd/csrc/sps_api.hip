@@ -1,0 +1,379 @@
+// sps_api.hip - the C interface of libsps: plans, argument checks, launches.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "sps_internal.h"
+
+struct sps_plan {
+  int32_t ndm;
+  int32_t nsamp;
+  int32_t max_width;
+  int32_t baseline_len;
+  float thresh;
+  int32_t nw;
+  int32_t nblocks;
+  double sqrtw[sps::kMaxWidths];
+  int64_t max_cands;
+  // tuning (never changes results)
+  int32_t stats_seg;   // blocks per baseline chain, 0 = auto
+  int32_t detect_seg;  // samples per detection segment, 0 = auto
+  int32_t hist_bins;   // 4096 or 16384
+  int device;
+  // scratch owned by the plan
+  int32_t* d_med;
+  int32_t* d_mad;
+  sps::RunSum* d_frag;
+  int64_t frag_cap;    // RunSum records allocated
+  // plain per-stage path scratch (allocated on first use)
+  void* d_plain;
+  size_t plain_bytes;
+  // tracing: events recorded around kernels when timing is on
+  int timing;
+  std::vector<hipEvent_t>* ev_free;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>* ev_pending;
+  double stage_ms[SPS_NSTAGES];
+  int64_t nsearch;
+};
+
+namespace {
+
+thread_local int g_last_error = SPS_OK;
+
+int fail(int code) {
+  g_last_error = code;
+  return code;
+}
+
+int ok() {
+  g_last_error = SPS_OK;
+  return SPS_OK;
+}
+
+constexpr int kDetectStep = 1024;
+
+int auto_stats_seg(const sps_plan* p) {
+  if (p->stats_seg > 0) return p->stats_seg;
+  // ~10k chains fill 256 CUs x ~20 resident waves twice over; keep each
+  // chain >= 4 windows long so the warm-up recount stays a small overhead.
+  const int64_t want_chains = 10240;
+  int64_t per_row = (want_chains + p->ndm - 1) / p->ndm;
+  if (per_row < 1) per_row = 1;
+  int64_t seg = (p->nblocks + per_row - 1) / per_row;
+  const int64_t min_seg = std::max<int64_t>(64, (4LL * p->baseline_len + 63) / 64);
+  if (seg < min_seg) seg = min_seg;
+  if (seg > p->nblocks) seg = p->nblocks;
+  if (seg < 1) seg = 1;
+  return (int)seg;
+}
+
+int auto_detect_seg(const sps_plan* p) {
+  int64_t seg = p->detect_seg;
+  if (seg <= 0) {
+    // ~4096 workgroups; each segment >= 4 x max_width so the halo stays small
+    const int64_t total = (int64_t)p->ndm * p->nsamp;
+    seg = total / 4096;
+    seg = std::max<int64_t>(seg, 4LL * p->max_width);
+  }
+  seg = ((seg + kDetectStep - 1) / kDetectStep) * kDetectStep;
+  if (seg < kDetectStep) seg = kDetectStep;
+  const int64_t nmax = ((int64_t)p->nsamp + kDetectStep - 1) / kDetectStep * kDetectStep;
+  if (seg > nmax) seg = nmax;
+  return (int)seg;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+hipEvent_t take_event(sps_plan* p) {
+  if (!p->ev_free->empty()) {
+    hipEvent_t e = p->ev_free->back();
+    p->ev_free->pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records an event on `s` when timing is on; returns it (or null).
+hipEvent_t mark(sps_plan* p, hipStream_t s) {
+  if (!p->timing) return nullptr;
+  hipEvent_t e = take_event(p);
+  if (e && hipEventRecord(e, s) != hipSuccess) {
+    (void)hipGetLastError();
+    p->ev_free->push_back(e);
+    return nullptr;
+  }
+  return e;
+}
+
+void span(sps_plan* p, int stage, hipEvent_t a, hipEvent_t b) {
+  if (a && b) p->ev_pending->push_back({stage, {a, b}});
+}
+
+// Make room for the run summaries of multi-segment rows (host-synchronous).
+int ensure_frag(sps_plan* p) {
+  const int64_t seg = auto_detect_seg(p);
+  const int64_t nseg = (p->nsamp + seg - 1) / seg;
+  const int64_t need = nseg > 1 ? (int64_t)p->ndm * p->nw * nseg : 0;
+  if (need <= p->frag_cap) return SPS_OK;
+  if (p->d_frag) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p->d_frag);
+    p->d_frag = nullptr;
+    p->frag_cap = 0;
+  }
+  if (hipMalloc(&p->d_frag, (size_t)need * sizeof(sps::RunSum)) != hipSuccess) {
+    (void)hipGetLastError();
+    p->d_frag = nullptr;
+    return SPS_ERR_OOM;
+  }
+  p->frag_cap = need;
+  return SPS_OK;
+}
+
+}  // namespace
+
+static int launch_stats(sps_plan* p, const float* d_series, hipStream_t stream, int32_t* d_median,
+                        int32_t* d_mad);
+
+extern "C" {
+
+int sps_last_error(void) { return g_last_error; }
+
+const char* sps_error_string(int code) {
+  switch (code) {
+    case SPS_OK: return "success";
+    case SPS_ERR_INVALID_ARG: return "invalid argument";
+    case SPS_ERR_OOM: return "device memory allocation failed";
+    case SPS_ERR_HIP: return "HIP runtime error";
+    case SPS_ERR_OVERFLOW: return "candidate buffer overflow";
+    case SPS_ERR_DOMAIN: return "input outside the supported domain";
+    default: return "unknown error";
+  }
+}
+
+sps_plan* sps_plan_create(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baseline_len, float snr_thresh) {
+  if (ndm < 1 || nsamp < 1 || nsamp > (int64_t)INT32_MAX - 8192 || !is_pow2(max_width) ||
+      max_width > SPS_MAX_WIDTH_LIMIT || baseline_len < 1 || baseline_len > SPS_MAX_BASELINE_LEN ||
+      !std::isfinite(snr_thresh) || !(snr_thresh > 0.0f)) {
+    fail(SPS_ERR_INVALID_ARG);
+    return nullptr;
+  }
+  sps_plan* p = new (std::nothrow) sps_plan;
+  if (!p) {
+    fail(SPS_ERR_OOM);
+    return nullptr;
+  }
+  std::memset(p, 0, sizeof(*p));
+  p->ev_free = new (std::nothrow) std::vector<hipEvent_t>();
+  p->ev_pending = new (std::nothrow) std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>();
+  if (!p->ev_free || !p->ev_pending) {
+    delete p->ev_free;
+    delete p->ev_pending;
+    delete p;
+    fail(SPS_ERR_OOM);
+    return nullptr;
+  }
+  p->ndm = ndm;
+  p->nsamp = (int32_t)nsamp;
+  p->max_width = max_width;
+  p->baseline_len = baseline_len;
+  p->thresh = snr_thresh;
+  p->nblocks = (int32_t)((nsamp + sps::kStride - 1) / sps::kStride);
+  p->nw = 0;
+  for (int w = 1; w <= max_width; w <<= 1) {
+    p->sqrtw[p->nw] = std::sqrt((double)w);  // correctly rounded (IEEE sqrt)
+    ++p->nw;
+  }
+  p->max_cands = 1LL << 24;
+  p->hist_bins = 4096;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p->ev_free;
+    delete p->ev_pending;
+    delete p;
+    fail(SPS_ERR_HIP);
+    return nullptr;
+  }
+  const size_t stats_bytes = (size_t)ndm * p->nblocks * sizeof(int32_t);
+  if (hipMalloc(&p->d_med, stats_bytes) != hipSuccess || hipMalloc(&p->d_mad, stats_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    sps_plan_destroy(p);
+    fail(SPS_ERR_OOM);
+    return nullptr;
+  }
+  if (ensure_frag(p) != SPS_OK) {
+    sps_plan_destroy(p);
+    fail(SPS_ERR_OOM);
+    return nullptr;
+  }
+  ok();
+  return p;
+}
+
+void sps_plan_destroy(sps_plan* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  if (p->d_med) (void)hipFree(p->d_med);
+  if (p->d_mad) (void)hipFree(p->d_mad);
+  if (p->d_frag) (void)hipFree(p->d_frag);
+  if (p->d_plain) (void)hipFree(p->d_plain);
+  if (p->ev_pending) {
+    for (auto& e : *p->ev_pending) {
+      (void)hipEventDestroy(e.second.first);
+      (void)hipEventDestroy(e.second.second);
+    }
+    delete p->ev_pending;
+  }
+  if (p->ev_free) {
+    for (auto e : *p->ev_free) (void)hipEventDestroy(e);
+    delete p->ev_free;
+  }
+  delete p;
+}
+
+int sps_timing_read(sps_plan* p, double* ms_out, int64_t* nsearch) {
+  if (!p || !ms_out || !nsearch) return fail(SPS_ERR_INVALID_ARG);
+  for (auto& e : *p->ev_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(e.second.second) != hipSuccess ||
+        hipEventElapsedTime(&ms, e.second.first, e.second.second) != hipSuccess) {
+      (void)hipGetLastError();
+      ms = 0.f;
+    }
+    p->stage_ms[e.first] += ms;
+    // an event may close one span and open the next: return each once
+    bool dup_a = false, dup_b = false;
+    for (auto f : *p->ev_free) { dup_a |= f == e.second.first; dup_b |= f == e.second.second; }
+    if (!dup_a) p->ev_free->push_back(e.second.first);
+    if (!dup_b && e.second.second != e.second.first) p->ev_free->push_back(e.second.second);
+  }
+  p->ev_pending->clear();
+  for (int i = 0; i < SPS_NSTAGES; ++i) {
+    ms_out[i] = p->stage_ms[i];
+    p->stage_ms[i] = 0.0;
+  }
+  *nsearch = p->nsearch;
+  p->nsearch = 0;
+  return ok();
+}
+
+int sps_plan_set(sps_plan* p, int attr, int64_t v) {
+  if (!p) return fail(SPS_ERR_INVALID_ARG);
+  switch (attr) {
+    case SPS_ATTR_MAX_CANDS:
+      if (v < 0 || v > (int64_t)UINT32_MAX) return fail(SPS_ERR_INVALID_ARG);
+      p->max_cands = v;
+      return ok();
+    case SPS_ATTR_STATS_SEG:
+      if (v < 0 || v > INT32_MAX) return fail(SPS_ERR_INVALID_ARG);
+      p->stats_seg = (int32_t)v;
+      return ok();
+    case SPS_ATTR_DETECT_SEG:
+      if (v < 0 || v > INT32_MAX || (v % kDetectStep) != 0) return fail(SPS_ERR_INVALID_ARG);
+      p->detect_seg = (int32_t)v;
+      if (ensure_frag(p) != SPS_OK) return fail(SPS_ERR_OOM);
+      return ok();
+    case SPS_ATTR_HIST_BINS:
+      if (v != 4096 && v != 16384) return fail(SPS_ERR_INVALID_ARG);
+      p->hist_bins = (int32_t)v;
+      return ok();
+    case SPS_ATTR_TIMING:
+      if (v != 0 && v != 1) return fail(SPS_ERR_INVALID_ARG);
+      p->timing = (int)v;
+      return ok();
+    default:
+      return fail(SPS_ERR_INVALID_ARG);
+  }
+}
+
+int sps_plan_get(const sps_plan* p, int attr, int64_t* v) {
+  if (!p || !v) return fail(SPS_ERR_INVALID_ARG);
+  switch (attr) {
+    case SPS_ATTR_MAX_CANDS: *v = p->max_cands; break;
+    case SPS_ATTR_STATS_SEG: *v = auto_stats_seg(p); break;
+    case SPS_ATTR_DETECT_SEG: *v = auto_detect_seg(p); break;
+    case SPS_ATTR_HIST_BINS: *v = p->hist_bins; break;
+    case SPS_ATTR_TIMING: *v = p->timing; break;
+    case SPS_ATTR_NBLOCKS: *v = p->nblocks; break;
+    case SPS_ATTR_NWIDTHS: *v = p->nw; break;
+    default: return fail(SPS_ERR_INVALID_ARG);
+  }
+  return ok();
+}
+
+int sps_block_stats(sps_plan* p, const float* d_series, hipStream_t stream, int32_t* d_median, int32_t* d_mad) {
+  if (!p || !d_series || !d_median || !d_mad) return fail(SPS_ERR_INVALID_ARG);
+  hipEvent_t e0 = mark(p, stream);
+  const int rc = launch_stats(p, d_series, stream, d_median, d_mad);
+  span(p, 0, e0, mark(p, stream));
+  return rc;
+}
+
+}  // extern "C"
+
+static int launch_stats(sps_plan* p, const float* d_series, hipStream_t stream, int32_t* d_median, int32_t* d_mad) {
+  sps::StatsArgs a;
+  a.x = d_series;
+  a.ld = p->nsamp;
+  a.N = p->nsamp;
+  a.L = p->baseline_len;
+  a.nblocks = p->nblocks;
+  a.seg_blocks = auto_stats_seg(p);
+  a.nseg = (p->nblocks + a.seg_blocks - 1) / a.seg_blocks;
+  a.nchains = p->ndm * a.nseg;
+  a.med = d_median;
+  a.mad = d_mad;
+  if (sps::launch_block_stats(a, p->hist_bins, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  return ok();
+}
+
+extern "C" {
+
+int sps_search(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand) {
+  if (!p || !d_series || !d_ncand || (!d_cands && p->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+  sps::DetectArgs d;
+  d.seg_len = auto_detect_seg(p);
+  d.nseg = (p->nsamp + d.seg_len - 1) / d.seg_len;
+  if (d.nseg > 1 && (int64_t)p->ndm * p->nw * d.nseg > p->frag_cap) return fail(SPS_ERR_INVALID_ARG);
+  hipEvent_t e0 = mark(p, stream);
+  if (sps::launch_zero_u32(d_ncand, 1, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  hipEvent_t e1 = mark(p, stream);
+  if (launch_stats(p, d_series, stream, p->d_med, p->d_mad) != SPS_OK) return g_last_error;
+  hipEvent_t e2 = mark(p, stream);
+  d.x = d_series;
+  d.ld = p->nsamp;
+  d.N = p->nsamp;
+  d.nblocks = p->nblocks;
+  d.nw = p->nw;
+  d.maxw = p->max_width;
+  d.med = p->d_med;
+  d.mad = p->d_mad;
+  d.theta = (double)p->thresh;
+  for (int j = 0; j < sps::kMaxWidths; ++j) d.sqrtw[j] = j < p->nw ? p->sqrtw[j] : 0.0;
+  d.rows = p->ndm;
+  d.row_offset = 0;
+  d.cands = d_cands;
+  d.ncand = d_ncand;
+  d.cap = (uint32_t)p->max_cands;
+  d.frag = p->d_frag;
+  if (sps::launch_detect(d, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  hipEvent_t e3 = mark(p, stream);
+  if (sps::launch_fixup(d, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  hipEvent_t e4 = mark(p, stream);
+  span(p, 2, e0, e1);
+  span(p, 0, e1, e2);
+  span(p, 1, e2, e3);
+  span(p, 2, e3, e4);
+  if (p->timing) ++p->nsearch;
+  return ok();
+}
+
+int sps_search_plain(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand) {
+  (void)p; (void)d_series; (void)stream; (void)d_cands; (void)d_ncand;
+  return fail(SPS_ERR_INVALID_ARG);  // provided by the per-stage path (sps_plain.hip)
+}
+
+}  // extern "C"

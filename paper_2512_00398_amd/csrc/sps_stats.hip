@@ -1,0 +1,339 @@
+// sps_stats.hip - baseline removal and normalisation stages (Heimdall++,
+// Section II-B): per 64-sample block k of every row, the lower median m_k and
+// the lower median absolute deviation MAD_k of the trailing window
+// W_k = x[max(0, e_k - L) : e_k], e_k = min(64k + 64, N). Results are exact.
+//
+// Design (gfx950, wave64). One wave owns one "chain": a contiguous run of
+// blocks of one row, walked in order. The wave keeps a counting histogram of
+// its window in LDS: NB consecutive integer values starting at `base`, two
+// 16-bit counts per 32-bit word (window sizes are < 2^16, and packed
+// add/subtract is exact modulo 2^32 once every count is back in [0, 2^16)).
+// Moving from block k-1 to k inserts the <= 64 new samples and removes the
+// <= 64 samples that left the window (one LDS atomic per sample). Beside the
+// histogram the wave tracks exact counts #{x < p} at three pivots: the
+// current median m, the lower edge m - MAD and the upper edge m + MAD + 1;
+// ballots update them for every inserted/removed sample, in or out of the
+// histogram's range. The common query reads 64 bins around each pivot, one
+// bin per lane, and finds the new median and MAD with three wave prefix sums
+// and two lane shuffles. When a quantity moves further than the 64-bin
+// windows, a full scan of the histogram answers; when it leaves the histogram
+// range the window is recounted around the exact median (radix select over
+// the window in global memory), and data too spread for any placement of the
+// histogram is answered block by block by radix select.
+#include "sps_internal.h"
+#include "sps_wave.h"
+
+namespace sps {
+
+namespace {
+
+__device__ __forceinline__ int ld_int(const float* row, int t) { return __float2int_rz(row[t]); }
+
+__device__ __forceinline__ uint32_t absdiff(int v, int m) {
+  return v >= m ? (uint32_t)v - (uint32_t)m : (uint32_t)m - (uint32_t)v;
+}
+
+__device__ __forceinline__ void hist_add(uint32_t* H, uint32_t idx, uint32_t one) {
+  // one = 1 (insert) or 0xFFFFFFFF (remove); the count lives in the idx&1 half
+  atomicAdd(&H[idx >> 1], one << ((idx & 1u) << 4));
+}
+
+__device__ __forceinline__ int hist_get(const uint32_t* H, int idx) {
+  return (int)((H[idx >> 1] >> ((idx & 1) << 4)) & 0xFFFFu);
+}
+
+template <int NB>
+struct Chain {
+  uint32_t* H;        // this wave's NB/2 histogram words
+  const float* row;
+  int L;
+  int lane;
+  int base;           // value of histogram bin 0
+  int n;              // window size
+  int m, cm;          // median, #{x < m}
+  int d, cL, cU;      // MAD, #{x < m - d}, #{x < m + d + 1}
+  bool raw;           // histogram not maintained (data too spread)
+};
+
+// Element of 0-based rank `rank` of the keys of samples [lo, hi):
+// MODE 0 keys are x ^ 0x80000000 (order of int32 x), MODE 1 keys are |x - m|.
+// Four passes over the window, 8 key bits each; H[0..255] serves as the
+// digit histogram (callers rebuild or abandon the value histogram afterwards).
+template <int MODE>
+__device__ uint32_t radix_select(uint32_t* H, const float* row, int lo, int hi, int rank, int m, int lane) {
+  uint32_t prefix = 0, pmask = 0;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int i = lane; i < 256; i += 64) H[i] = 0;
+    wave_lds_fence();
+    for (int t0 = lo; t0 < hi; t0 += 64) {
+      const int t = t0 + lane;
+      if (t < hi) {
+        const int v = ld_int(row, t);
+        const uint32_t key = MODE == 0 ? ((uint32_t)v ^ 0x80000000u) : absdiff(v, m);
+        if ((key & pmask) == prefix) atomicAdd(&H[(key >> shift) & 255u], 1u);
+      }
+    }
+    wave_lds_fence();
+    const int c0 = (int)H[4 * lane], c1 = (int)H[4 * lane + 1], c2 = (int)H[4 * lane + 2];
+    const int c3 = (int)H[4 * lane + 3];
+    const int s = c0 + c1 + c2 + c3;
+    const int inc = wave_scan_incl(s);
+    const int j = ctz(ballot(inc > rank));  // total count > rank, so some lane qualifies
+    int r = rank - (readlane(inc, j) - readlane(s, j));
+    const int d0 = readlane(c0, j), d1 = readlane(c1, j), d2 = readlane(c2, j);
+    int dig = 4 * j;
+    if (r >= d0) {
+      r -= d0; ++dig;
+      if (r >= d1) {
+        r -= d1; ++dig;
+        if (r >= d2) { r -= d2; ++dig; }
+      }
+    }
+    rank = r;
+    prefix |= (uint32_t)dig << shift;
+    pmask |= 0xFFu << shift;
+    wave_lds_fence();
+  }
+  return prefix;
+}
+
+// Recount the window [lo, hi) into a histogram whose bin 0 is `base`;
+// returns #{x < base}.
+template <int NB>
+__device__ int rebuild(Chain<NB>& c, int lo, int hi, int base) {
+  c.base = base;
+  for (int i = c.lane; i < NB / 2; i += 64) c.H[i] = 0;
+  wave_lds_fence();
+  int below = 0;
+  for (int t0 = lo; t0 < hi; t0 += 64) {
+    const int t = t0 + c.lane;
+    const bool ok = t < hi;
+    const int v = ok ? ld_int(c.row, t) : 0;
+    const uint32_t idx = (uint32_t)v - (uint32_t)base;
+    if (ok && idx < (uint32_t)NB) hist_add(c.H, idx, 1u);
+    below += popc(ballot(ok && v < base));
+  }
+  wave_lds_fence();
+  c.raw = false;
+  return below;
+}
+
+// Median and MAD from the whole histogram, given #{x < base}. Fails (returns
+// false) when a needed quantile lies outside the histogram's range.
+template <int NB>
+__device__ bool full_query(Chain<NB>& c, int below) {
+  const int rho = (c.n - 1) >> 1;
+  if (below > rho) return false;
+  int acc = below, m2 = 0, cm2 = 0;
+  bool found = false;
+  for (int i0 = 0; i0 < NB; i0 += 64) {
+    const int h = hist_get(c.H, i0 + c.lane);
+    const int inc = wave_scan_incl(h);
+    const uint64_t mk = ballot(acc + inc > rho);
+    if (mk) {
+      const int j = ctz(mk);
+      m2 = c.base + i0 + j;
+      cm2 = acc + readlane(inc, j) - readlane(h, j);
+      found = true;
+      break;
+    }
+    acc += readlane(inc, 63);
+  }
+  if (!found) return false;
+  // MAD: fold the histogram at m2; g(0) = h(m2), g(e) = h(m2 + e) + h(m2 - e).
+  const int i2 = m2 - c.base;
+  int acc_lo = 0, acc_hi = 0;
+  for (int e0 = 0;; e0 += 64) {
+    const int e = e0 + c.lane;
+    const bool in_hi = i2 + e < NB, in_lo = i2 - e >= 0;
+    const int ghi = in_hi ? hist_get(c.H, i2 + e) : 0;
+    const int glo = (e > 0 && in_lo) ? hist_get(c.H, i2 - e) : 0;
+    const int ihi = wave_scan_incl(ghi), ilo = wave_scan_incl(glo);
+    const bool ok = in_hi && in_lo;
+    const uint64_t okm = ballot(ok);
+    const uint64_t mk = ballot(ok && acc_lo + acc_hi + ihi + ilo > rho);
+    if (mk) {  // okm is a prefix of the lanes, so every e <= j was in range
+      const int j = ctz(mk);
+      c.m = m2;
+      c.cm = cm2;
+      c.d = e0 + j;
+      c.cL = cm2 - (acc_lo + readlane(ilo, j));
+      c.cU = cm2 + acc_hi + readlane(ihi, j);
+      return true;
+    }
+    if (okm != ~0ull) return false;
+    acc_lo += readlane(ilo, 63);
+    acc_hi += readlane(ihi, 63);
+  }
+}
+
+// Local query: new median within 31 values of the old one and new MAD within
+// 31 of the old one (the usual case). Returns false when it cannot decide.
+template <int NB>
+__device__ __forceinline__ bool fast_query(Chain<NB>& c) {
+  const int rho = (c.n - 1) >> 1;
+  const int im = c.m - c.base, iL = c.m - c.d - c.base, iU = c.m + c.d + 1 - c.base;
+  if (im - 32 < 0 || im + 32 > NB || iL - 32 < 0 || iU + 32 > NB) return false;
+  const int lane = c.lane;
+  const int h = hist_get(c.H, im - 32 + lane);
+  const int hL = hist_get(c.H, iL - 32 + lane);
+  const int hU = hist_get(c.H, iU - 32 + lane);
+  const int inc = wave_scan_incl(h), incL = wave_scan_incl(hL), incU = wave_scan_incl(hU);
+  const int lt = c.cm - readlane(inc, 31) + inc - h;  // #{x < m - 32 + lane}
+  const uint64_t mk = ballot(lt + h > rho);
+  if (!mk) return false;
+  const int j = ctz(mk);
+  const int ltj = readlane(lt, j);
+  if (ltj > rho) return false;  // median below the window
+  const int delta = j - 32;      // new median - old median
+  const int ltL = c.cL - readlane(incL, 31) + incL - hL;  // #{x < (m - d) - 32 + lane}
+  const int ltU = c.cU - readlane(incU, 31) + incU - hU;  // #{x < (m + d + 1) - 32 + lane}
+  // lane tests d' = d + lane - 32 around the new median m + delta:
+  // #{|x - m'| <= d'} = #{x < m' + d' + 1} - #{x < m' - d'}
+  const int a = delta + 64 - lane, b = delta + lane;
+  const int dp = c.d + lane - 32;
+  const bool ok = a >= 0 && a < 64 && b >= 0 && b < 64 && dp >= 0;
+  const int va = __shfl(ltL, a & 63, 64), vb = __shfl(ltU, b & 63, 64);
+  const uint64_t okm = ballot(ok), fm = ballot(ok && vb - va > rho);
+  if (!fm) return false;
+  const int jj = ctz(fm);
+  if (jj == ctz(okm) && readlane(dp, jj) > 0) return false;  // MAD may be smaller still
+  c.m = c.m + delta;
+  c.cm = ltj;
+  c.d = readlane(dp, jj);
+  c.cL = readlane(va, jj);
+  c.cU = readlane(vb, jj);
+  return true;
+}
+
+// Exact answer for window [lo, hi) from the samples themselves, then a
+// histogram centred on the median when the data allow one.
+template <int NB>
+__device__ void exact_block(Chain<NB>& c, int lo, int hi) {
+  const int rho = (c.n - 1) >> 1;
+  const int m = (int)(radix_select<0>(c.H, c.row, lo, hi, rho, 0, c.lane) ^ 0x80000000u);
+  const uint32_t d = radix_select<1>(c.H, c.row, lo, hi, rho, m, c.lane);
+  c.m = m;
+  c.d = (int)d;
+  if (d < (uint32_t)(NB / 2 - 128)) {
+    const int below = rebuild(c, lo, hi, m - NB / 2);
+    const bool ok = full_query(c, below);  // succeeds: both quantiles are in range
+    c.raw = !ok;
+  } else {
+    c.raw = true;
+  }
+}
+
+template <int NB>
+__device__ void chain_init(Chain<NB>& c, int lo, int hi) {
+  // Centre the first histogram on the median of the last <= 256 window samples.
+  const int slo = max(lo, hi - 256);
+  const int g = (int)(radix_select<0>(c.H, c.row, slo, hi, (hi - slo - 1) >> 1, 0, c.lane) ^ 0x80000000u);
+  const int below = rebuild(c, lo, hi, g - NB / 2);
+  if (!full_query(c, below)) exact_block(c, lo, hi);
+}
+
+template <int NB>
+__device__ __forceinline__ void chain_step(Chain<NB>& c, int lo, int hi, bool a_ok, int av, bool b_ok, int bv) {
+  c.n += popc(ballot(a_ok)) - popc(ballot(b_ok));
+  if (c.raw) {
+    exact_block(c, lo, hi);
+    return;
+  }
+  const uint32_t ua = (uint32_t)av - (uint32_t)c.base, ub = (uint32_t)bv - (uint32_t)c.base;
+  if (a_ok && ua < (uint32_t)NB) hist_add(c.H, ua, 1u);
+  if (b_ok && ub < (uint32_t)NB) hist_add(c.H, ub, 0xFFFFFFFFu);
+  const int pL = c.m - c.d, pU = c.m + c.d + 1;
+  c.cm += popc(ballot(a_ok && av < c.m)) - popc(ballot(b_ok && bv < c.m));
+  c.cL += popc(ballot(a_ok && av < pL)) - popc(ballot(b_ok && bv < pL));
+  c.cU += popc(ballot(a_ok && av < pU)) - popc(ballot(b_ok && bv < pU));
+  wave_lds_fence();
+  if (fast_query(c)) return;
+  // #{x < base} from the exact count below the old median
+  const int im = c.m - c.base;
+  int s = 0;
+  for (int i0 = 0; i0 < im; i0 += 64) {
+    const int i = i0 + c.lane;
+    s += i < im ? hist_get(c.H, i) : 0;
+  }
+  const int below = c.cm - wave_sum(s);
+  if (full_query(c, below)) {
+    // keep the fast path's windows inside the histogram: recentre if close to an edge
+    if (c.m - c.d - 96 < c.base || c.m + c.d + 97 > c.base + NB) {
+      if (c.d < NB / 2 - 128) {
+        const int b2 = rebuild(c, lo, hi, c.m - NB / 2);
+        c.raw = !full_query(c, b2);
+      }
+    }
+    return;
+  }
+  exact_block(c, lo, hi);
+}
+
+// WPG chains (waves) per workgroup; LDS = WPG * NB * 2 bytes.
+template <int NB, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
+  __shared__ uint32_t hist[WPG][NB / 2];
+  const int wave = threadIdx.x >> 6;
+  const int lane = lane_id();
+  const int chain = blockIdx.x * WPG + wave;
+  if (chain >= a.nchains) return;  // whole wave leaves; no block barriers are used
+  const int row = chain / a.nseg;
+  const int seg = chain - row * a.nseg;
+  const int kb0 = seg * a.seg_blocks;
+  const int kb1 = min(a.nblocks, kb0 + a.seg_blocks);
+  const int N = a.N, L = a.L;
+  Chain<NB> c;
+  c.H = hist[wave];
+  c.row = a.x + (int64_t)row * a.ld;
+  c.L = L;
+  c.lane = lane;
+  int32_t* med = a.med + (int64_t)row * a.nblocks;
+  int32_t* mad = a.mad + (int64_t)row * a.nblocks;
+
+  {
+    const int e = min(kb0 * kStride + kStride, N), lo = max(0, e - L);
+    c.n = e - lo;
+    chain_init(c, lo, e);
+    if (lane == 0) { med[kb0] = c.m; mad[kb0] = c.d; }
+  }
+
+  // Samples entering / leaving the window at block kk, prefetched 4 blocks ahead.
+  auto fetch = [&](int kk, float& va, float& vb) {
+    const int ep = min(kk * kStride, N), e = min(kk * kStride + kStride, N);
+    const int lp = max(0, ep - L), l2 = max(0, e - L);
+    va = (lane < e - ep) ? c.row[ep + lane] : 0.f;
+    vb = (lane < l2 - lp) ? c.row[lp + lane] : 0.f;
+  };
+  float pa[4], pb[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) fetch(kb0 + 1 + j, pa[j], pb[j]);
+
+  for (int k = kb0 + 1; k < kb1; k += 4) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int kk = k + j;
+      const float va = pa[j], vb = pb[j];
+      fetch(kk + 4, pa[j], pb[j]);
+      if (kk < kb1) {
+        const int ep = min(kk * kStride, N), e = min(kk * kStride + kStride, N);
+        const int lp = max(0, ep - L), l2 = max(0, e - L);
+        chain_step(c, l2, e, lane < e - ep, __float2int_rz(va), lane < l2 - lp, __float2int_rz(vb));
+        if (lane == 0) { med[kk] = c.m; mad[kk] = c.d; }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_block_stats(const StatsArgs& a, int hist_bins, hipStream_t s) {
+  if (a.nchains <= 0) return hipSuccess;
+  if (hist_bins == 16384)
+    hipLaunchKernelGGL((k_block_stats<16384, 2>), dim3((a.nchains + 1) / 2), dim3(128), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_block_stats<4096, 4>), dim3((a.nchains + 3) / 4), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace sps

@@ -1,0 +1,220 @@
+"""Python binding of libsps (ctypes; argument marshalling only).
+
+Every step of the search runs in the HIP library. PyTorch provides device
+memory and streams. If the library is not built this module raises: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsps.so")
+
+SPS_OK = 0
+SPS_ERR_INVALID_ARG = -1
+SPS_ERR_OOM = -2
+SPS_ERR_HIP = -3
+SPS_ERR_OVERFLOW = -4
+SPS_ERR_DOMAIN = -5
+
+ATTR_MAX_CANDS = 1
+ATTR_STATS_SEG = 2
+ATTR_DETECT_SEG = 3
+ATTR_HIST_BINS = 4
+ATTR_TIMING = 5
+NSTAGES = 4
+STAGES = ("block_stats", "detect", "fixup", "plain")
+ATTR_NBLOCKS = 16
+ATTR_NWIDTHS = 17
+
+BLOCK_STRIDE = 64
+CAND_DTYPE = np.dtype([("sample", "<i4"), ("dm_idx", "<u4"), ("width", "<u4"), ("snr", "<f4")])
+
+# (name, restype, argtypes) of every exported entry point declared in include/sps.h
+_P = ctypes.c_void_p
+EXPORTS = [
+    ("sps_plan_create", _P, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float]),
+    ("sps_plan_destroy", None, [_P]),
+    ("sps_search", ctypes.c_int, [_P, _P, _P, _P, _P]),
+    ("sps_block_stats", ctypes.c_int, [_P, _P, _P, _P, _P]),
+    ("sps_search_plain", ctypes.c_int, [_P, _P, _P, _P, _P]),
+    ("sps_plan_set", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64]),
+    ("sps_plan_get", ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
+    ("sps_timing_read", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    ("sps_last_error", ctypes.c_int, []),
+    ("sps_error_string", ctypes.c_char_p, [ctypes.c_int]),
+]
+
+_lib = None
+
+
+class SpsError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (what, error_string(code), code))
+
+
+def load() -> ctypes.CDLL:
+    """Load the in-tree libsps.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsps.so is not built (run `python -m paper_2512_00398_amd.build`)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in EXPORTS:
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def error_string(code: int) -> str:
+    return load().sps_error_string(int(code)).decode()
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _check_series(x, ndm: int, nsamp: int):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float32:
+        raise TypeError("series must be a float32 tensor on the GPU")
+    if tuple(x.shape) != (ndm, nsamp) or not x.is_contiguous():
+        raise ValueError("series must be contiguous [%d][%d]" % (ndm, nsamp))
+
+
+class Plan:
+    """A search plan for blocks of ndm x nsamp samples (see include/sps.h)."""
+
+    def __init__(self, ndm: int, nsamp: int, max_width: int, baseline_len: int, snr_thresh: float):
+        lib = load()
+        self._h = lib.sps_plan_create(int(ndm), int(nsamp), int(max_width), int(baseline_len),
+                                      float(snr_thresh))
+        if not self._h:
+            raise SpsError(lib.sps_last_error(), "sps_plan_create")
+        self.ndm, self.nsamp = int(ndm), int(nsamp)
+        self.max_width, self.baseline_len, self.snr_thresh = int(max_width), int(baseline_len), float(snr_thresh)
+
+    # -- attributes
+    def set(self, attr: int, value: int) -> None:
+        rc = load().sps_plan_set(self._h, int(attr), int(value))
+        if rc:
+            raise SpsError(rc, "sps_plan_set")
+
+    def get(self, attr: int) -> int:
+        v = ctypes.c_int64()
+        rc = load().sps_plan_get(self._h, int(attr), ctypes.byref(v))
+        if rc:
+            raise SpsError(rc, "sps_plan_get")
+        return int(v.value)
+
+    @property
+    def nblocks(self) -> int:
+        return self.get(ATTR_NBLOCKS)
+
+    @property
+    def max_cands(self) -> int:
+        return self.get(ATTR_MAX_CANDS)
+
+    # -- buffers
+    def alloc_cands(self, capacity: Optional[int] = None):
+        import torch
+        cap = self.max_cands if capacity is None else int(capacity)
+        if capacity is not None and cap != self.max_cands:
+            self.set(ATTR_MAX_CANDS, cap)
+        cands = torch.empty((max(cap, 1), 4), dtype=torch.int32, device="cuda")
+        ncand = torch.zeros(1, dtype=torch.int32, device="cuda")
+        return cands, ncand
+
+    # -- entry points
+    def search(self, series, cands=None, ncand=None, stream=None, plain: bool = False):
+        """Enqueue a search; returns the (cands, ncand) device tensors."""
+        _check_series(series, self.ndm, self.nsamp)
+        if cands is None or ncand is None:
+            cands, ncand = self.alloc_cands()
+        if cands.shape[0] < self.max_cands:
+            raise ValueError("candidate buffer smaller than the plan's capacity")
+        fn = load().sps_search_plain if plain else load().sps_search
+        rc = fn(self._h, series.data_ptr(), _stream_handle(stream), cands.data_ptr(), ncand.data_ptr())
+        if rc:
+            raise SpsError(rc, "sps_search_plain" if plain else "sps_search")
+        return cands, ncand
+
+    def block_stats(self, series, med=None, mad=None, stream=None):
+        import torch
+        _check_series(series, self.ndm, self.nsamp)
+        nb = self.nblocks
+        if med is None:
+            med = torch.empty((self.ndm, nb), dtype=torch.int32, device="cuda")
+        if mad is None:
+            mad = torch.empty((self.ndm, nb), dtype=torch.int32, device="cuda")
+        rc = load().sps_block_stats(self._h, series.data_ptr(), _stream_handle(stream), med.data_ptr(),
+                                    mad.data_ptr())
+        if rc:
+            raise SpsError(rc, "sps_block_stats")
+        return med, mad
+
+    def timing_read(self):
+        """Summed ms per stage since the last read, and the number of searches (waits for the events)."""
+        ms = (ctypes.c_double * NSTAGES)()
+        n = ctypes.c_int64()
+        rc = load().sps_timing_read(self._h, ms, ctypes.byref(n))
+        if rc:
+            raise SpsError(rc, "sps_timing_read")
+        return dict(zip(STAGES, list(ms))), int(n.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().sps_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def cands_to_numpy(cands, ncand, capacity: Optional[int] = None) -> np.ndarray:
+    """Copy the first ncand records to a structured array sorted (dm, width, sample).
+
+    Raises SpsError(SPS_ERR_OVERFLOW) if the true count exceeds the capacity.
+    """
+    n = int(ncand.item()) & 0xFFFFFFFF
+    cap = cands.shape[0] if capacity is None else int(capacity)
+    if n > cap:
+        raise SpsError(SPS_ERR_OVERFLOW, "search (%d candidates, capacity %d)" % (n, cap))
+    a = cands[:n].cpu().numpy().view(CAND_DTYPE).reshape(-1)
+    if a.size:
+        a = a[np.lexsort((a["sample"], a["width"], a["dm_idx"]))]
+    return a
+
+
+def search(series, max_width: int, baseline_len: int, snr_thresh: float, capacity: Optional[int] = None,
+           plain: bool = False) -> np.ndarray:
+    """One-shot convenience: plan, search on the current stream, return sorted candidates."""
+    import torch
+    ndm, nsamp = series.shape
+    with Plan(ndm, nsamp, max_width, baseline_len, snr_thresh) as p:
+        if capacity is not None:
+            p.set(ATTR_MAX_CANDS, capacity)
+        cands, ncand = p.alloc_cands()
+        p.search(series, cands, ncand, plain=plain)
+        torch.cuda.synchronize()
+        return cands_to_numpy(cands, ncand, p.max_cands)

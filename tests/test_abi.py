@@ -1,0 +1,58 @@
+"""The C-ABI library: it loads, exports what include/sps.h declares, and rejects bad
+arguments before touching a device. No compute calls (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "sps.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sps_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    from paper_2512_00398_amd import sps
+    lib = sps.load()
+    declared = header_functions()
+    assert "sps_plan_create" in declared and "sps_search" in declared and "sps_plan_destroy" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(n for n, _, _ in sps.EXPORTS) == declared
+
+
+def test_invalid_plans_rejected_without_device():
+    from paper_2512_00398_amd import sps
+    lib = sps.load()
+    bad = [(0, 100, 4, 10, 6.0), (4, 0, 4, 10, 6.0), (4, 100, 3, 10, 6.0), (4, 100, 8192, 10, 6.0),
+           (4, 100, 4, 0, 6.0), (4, 100, 4, 70000, 6.0), (4, 100, 4, 10, 0.0), (4, 100, 4, 10, -1.0),
+           (4, 100, 4, 10, float("inf")), (4, 100, 4, 10, float("nan")), (4, 1 << 31, 4, 10, 6.0)]
+    for args in bad:
+        assert not lib.sps_plan_create(*args), args
+        assert lib.sps_last_error() == sps.SPS_ERR_INVALID_ARG
+
+
+def test_null_plan_calls_fail_cleanly():
+    from paper_2512_00398_amd import sps
+    lib = sps.load()
+    assert lib.sps_search(None, None, None, None, None) == sps.SPS_ERR_INVALID_ARG
+    assert lib.sps_block_stats(None, None, None, None, None) == sps.SPS_ERR_INVALID_ARG
+    assert lib.sps_plan_set(None, sps.ATTR_MAX_CANDS, 5) == sps.SPS_ERR_INVALID_ARG
+    v = ctypes.c_int64()
+    assert lib.sps_plan_get(None, sps.ATTR_MAX_CANDS, ctypes.byref(v)) == sps.SPS_ERR_INVALID_ARG
+    lib.sps_plan_destroy(None)
+    assert sps.error_string(0) == "success"
+    assert "overflow" in sps.error_string(sps.SPS_ERR_OVERFLOW)
+
+
+def test_binding_has_no_cpu_fallback():
+    # The product path must not import the oracle.
+    import paper_2512_00398_amd.sps as m
+    src = open(m.__file__).read()
+    assert "oracle" not in src.replace("no CPU fallback", "")
+    for f in os.listdir(os.path.join(ROOT, "paper_2512_00398_amd", "csrc")):
+        assert "oracle" not in open(os.path.join(ROOT, "paper_2512_00398_amd", "csrc", f)).read().lower()

@@ -1,0 +1,178 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Medians and MADs must be bit-exact; candidate sets identical except within
+1e-3*theta of the threshold; S/N within 1e-4 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import compare_cands, exact_equal
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def sps():
+    from paper_2512_00398_amd import sps as m
+    return m
+
+
+def to_dev(x):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def gpu_search(x, max_width, L, theta, detect_seg=0, stats_seg=0, hist_bins=4096, capacity=None, plain=False):
+    torch = _torch()
+    m = sps()
+    xd = to_dev(x)
+    ndm, n = x.shape
+    with m.Plan(ndm, n, max_width, L, theta) as p:
+        if detect_seg:
+            p.set(m.ATTR_DETECT_SEG, detect_seg)
+        if stats_seg:
+            p.set(m.ATTR_STATS_SEG, stats_seg)
+        p.set(m.ATTR_HIST_BINS, hist_bins)
+        if capacity is not None:
+            p.set(m.ATTR_MAX_CANDS, capacity)
+        cands, ncand = p.alloc_cands()
+        p.search(xd, cands, ncand, plain=plain)
+        med, mad = p.block_stats(xd)
+        torch.cuda.synchronize()
+        return m.cands_to_numpy(cands, ncand, p.max_cands), med.cpu().numpy(), mad.cpu().numpy()
+
+
+def check(x, max_width, L, theta, where, **kw):
+    print("case %s shape=%s w=%d L=%d theta=%g %s" % (where, x.shape, max_width, L, theta, kw), flush=True)
+    sys.stdout.flush()
+    got, med, mad = gpu_search(x, max_width, L, theta, **kw)
+    ref, rm, rmad = oracle.search(x, max_width, L, theta, with_stats=True)
+    assert np.array_equal(med, rm), "%s: medians differ at %s" % (where, np.argwhere(med != rm)[:5])
+    assert np.array_equal(mad, rmad), "%s: MADs differ at %s" % (where, np.argwhere(mad != rmad)[:5])
+    ex = compare_cands(got, ref, theta, where)
+    return got, ref, ex
+
+
+def test_small_config_parity():
+    cfg = synth.config(1)["blocks"][0]
+    x = synth.generate(cfg)
+    got, ref, ex = check(x, cfg.max_width, cfg.baseline_len, cfg.snr_thresh, "c1")
+    assert ex == 0 and exact_equal(got, ref)
+    assert ref.size > 1000
+
+
+@pytest.mark.parametrize("detect_seg,stats_seg", [(1024, 64), (2048, 100), (4096, 333), (0, 256)])
+def test_tilings_give_identical_results(detect_seg, stats_seg):
+    cfg = synth.config(1)["blocks"][0]
+    x = synth.generate(cfg)
+    got, ref, ex = check(x, cfg.max_width, cfg.baseline_len, cfg.snr_thresh, "c1-tiles",
+                         detect_seg=detect_seg, stats_seg=stats_seg)
+    assert ex == 0 and exact_equal(got, ref)
+
+
+def _edge_cases():
+    rng = np.random.default_rng(7)
+    cases = []
+    # ragged lengths, tiny rows, window longer than the row
+    for n, L, w in [(1, 5, 1), (63, 16, 16), (64, 64, 32), (65, 4096, 64), (1000, 100, 512), (3001, 700, 4096)]:
+        x = np.round(rng.normal(1000, 30, size=(3, n)))
+        x[:, n // 2: n // 2 + 3] += 400
+        cases.append(("ragged-%d" % n, x, w, L, 3.0))
+    # constant rows (MAD = 0 everywhere) next to a noisy row
+    x = np.full((2, 5000), 777.0)
+    x[1] = np.round(rng.normal(0, 5, size=5000))
+    cases.append(("constant", x, 64, 512, 2.0))
+    # heavy ties (values in {0,1,2}) and steps that move the median far and fast
+    x = rng.integers(0, 3, size=(2, 9000)).astype(np.float64)
+    x[1, 3000:] += 20000
+    x[1, 6000:] -= 45000
+    cases.append(("ties-steps", x, 128, 1000, 1.5))
+    # spread wider than any histogram placement (exact radix fallback)
+    x = np.round(rng.uniform(-4e6, 4e6, size=(2, 6000)))
+    cases.append(("wide", x, 256, 900, 2.5))
+    # negative values and a large DC level near the domain limit
+    x = np.round(rng.normal(-8e6, 40, size=(2, 7000)))
+    x[0, 4000:4010] += 900
+    cases.append(("negative", x, 64, 2000, 4.0))
+    return cases
+
+
+@pytest.mark.parametrize("name,x,w,L,theta", _edge_cases(), ids=[c[0] for c in _edge_cases()])
+def test_edge_cases(name, x, w, L, theta):
+    got, ref, ex = check(x.astype(np.float32), w, L, theta, name)
+    assert exact_equal(got, ref)
+    got2, _, _ = check(x.astype(np.float32), w, L, theta, name + "-seg", detect_seg=1024, stats_seg=64)
+    assert exact_equal(got2, ref)
+
+
+def test_histogram_span_variant():
+    cfg = synth.config(1)["blocks"][0]
+    x = synth.generate(cfg, rows=range(16))
+    got, ref, ex = check(x, cfg.max_width, cfg.baseline_len, cfg.snr_thresh, "hist16k", hist_bins=16384)
+    assert exact_equal(got, ref)
+
+
+def test_overflow_reports_true_count():
+    cfg = synth.config(1)["blocks"][0]
+    x = synth.generate(cfg)
+    m = sps()
+    torch = _torch()
+    ref = oracle.search(x, cfg.max_width, cfg.baseline_len, cfg.snr_thresh)
+    with m.Plan(*x.shape, cfg.max_width, cfg.baseline_len, cfg.snr_thresh) as p:
+        p.set(m.ATTR_MAX_CANDS, 100)
+        cands, ncand = p.alloc_cands()
+        p.search(to_dev(x), cands, ncand)
+        torch.cuda.synchronize()
+        assert int(ncand.item()) == ref.size
+        with pytest.raises(m.SpsError):
+            m.cands_to_numpy(cands, ncand, 100)
+        # the records that were written are genuine candidates
+        part = cands[:100].cpu().numpy().view(m.CAND_DTYPE).reshape(-1)
+        refk = set(zip(ref["dm_idx"].tolist(), ref["width"].tolist(), ref["sample"].tolist()))
+        assert all(k in refk for k in zip(part["dm_idx"].tolist(), part["width"].tolist(), part["sample"].tolist()))
+
+
+def test_invalid_arguments_are_rejected():
+    m = sps()
+    for args in [(0, 100, 4, 10, 6.0), (4, 0, 4, 10, 6.0), (4, 100, 3, 10, 6.0), (4, 100, 8192, 10, 6.0),
+                 (4, 100, 4, 0, 6.0), (4, 100, 4, 70000, 6.0), (4, 100, 4, 10, 0.0), (4, 100, 4, 10, float("nan"))]:
+        with pytest.raises(m.SpsError):
+            m.Plan(*args)
+
+
+def test_large_config_sampled_rows():
+    # The single-large-file workload at full size; the oracle checks sampled rows.
+    cfg = synth.config(2)["blocks"][0]
+    torch = _torch()
+    m = sps()
+    print("case c2 full size: generate", flush=True)
+    x = synth.generate(cfg)
+    xd = to_dev(x)
+    rows = [0, 1, 511, 1023]
+    with m.Plan(cfg.ndm, cfg.nsamp, cfg.max_width, cfg.baseline_len, cfg.snr_thresh) as p:
+        cands, ncand = p.alloc_cands()
+        print("case c2: search", flush=True)
+        p.search(xd, cands, ncand)
+        med, mad = p.block_stats(xd)
+        torch.cuda.synchronize()
+        got = m.cands_to_numpy(cands, ncand, p.max_cands)
+        med = med.cpu().numpy()
+        mad = mad.cpu().numpy()
+    print("case c2: oracle on rows %s (%d gpu candidates)" % (rows, got.size), flush=True)
+    ref, rm, rmad = oracle.search(x, cfg.max_width, cfg.baseline_len, cfg.snr_thresh, rows=rows, with_stats=True)
+    assert np.array_equal(med[rows], rm) and np.array_equal(mad[rows], rmad)
+    sel = np.isin(got["dm_idx"], rows)
+    assert compare_cands(got[sel], ref, cfg.snr_thresh, "c2-rows") == 0
+    assert exact_equal(got[sel], ref)
+    # every candidate is well-formed
+    assert got["dm_idx"].max() < cfg.ndm and (got["sample"] >= 0).all()
+    assert (got["sample"].astype(np.int64) + got["width"] <= cfg.nsamp).all()
+    assert (got["snr"] > cfg.snr_thresh).all()
