@@ -256,7 +256,7 @@ __device__ __forceinline__ void chain_step(Chain<NB>& c, int lo, int hi, bool a_
     const int i = i0 + c.lane;
     s += i < im ? hist_get(c.H, i) : 0;
   }
-  const int below = c.cm - wave_sum(s);
+  const int below = c.cm - wave_sum_u(s);
   if (full_query(c, below)) {
     // keep the fast path's windows inside the histogram: recentre if close to an edge
     if (c.m - c.d - 96 < c.base || c.m + c.d + 97 > c.base + NB) {

@@ -35,27 +35,48 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Inclusive prefix sum over the 64 lanes.
+// DPP lane move: lanes whose source is outside the row, or whose row/bank is
+// masked off, receive `old`. Controls (GFX9 encoding): row_shr:n = 0x110+n,
+// row_mirror = 0x140, row_half_mirror = 0x141, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143, quad_perm = 0x00..0xff.
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ __forceinline__ int dpp(int old, int src) {
+  return __builtin_amdgcn_update_dpp(old, src, CTRL, ROW_MASK, BANK_MASK, false);
+}
+
+// Inclusive prefix sum over the 64 lanes (Hillis-Steele within rows of 16,
+// then row broadcasts).
 __device__ __forceinline__ int wave_scan_incl(int v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int t = __shfl_up(v, o, 64);
-    v += (l >= o) ? t : 0;
-  }
+  v += dpp<0x111>(0, v);
+  v += dpp<0x112>(0, v);
+  v += dpp<0x114>(0, v);
+  v += dpp<0x118>(0, v);
+  v += dpp<0x142, 0xa>(0, v);
+  v += dpp<0x143, 0xc>(0, v);
   return v;
 }
 
-__device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Maximum over the 64 lanes, returned wave-uniform.
+__device__ __forceinline__ int wave_max_u(int v) {
+  v = max(v, dpp<0xb1>(v, v));        // quad_perm [1,0,3,2]
+  v = max(v, dpp<0x4e>(v, v));        // quad_perm [2,3,0,1]
+  v = max(v, dpp<0x141>(v, v));       // row_half_mirror
+  v = max(v, dpp<0x140>(v, v));       // row_mirror
+  v = max(v, dpp<0x142, 0xa>(v, v));  // row_bcast:15
+  v = max(v, dpp<0x143, 0xc>(v, v));  // row_bcast:31
+  return readlane(v, 63);
 }
 
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
+// Sum over the 64 lanes, returned wave-uniform.
+__device__ __forceinline__ int wave_sum_u(int v) { return readlane(wave_scan_incl(v), 63); }
+
+// Lanes lo..hi (inclusive, clipped to 0..63) as a mask; empty if lo > hi.
+__device__ __forceinline__ uint64_t lane_range(int lo, int hi) {
+  lo = lo < 0 ? 0 : lo;
+  hi = hi > 63 ? 63 : hi;
+  if (lo > hi) return 0ull;
+  const uint64_t upto = hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull);
+  return upto & (~0ull << lo);
 }
 
 }  // namespace sps

@@ -175,4 +175,4 @@ def test_large_config_sampled_rows():
     # every candidate is well-formed
     assert got["dm_idx"].max() < cfg.ndm and (got["sample"] >= 0).all()
     assert (got["sample"].astype(np.int64) + got["width"] <= cfg.nsamp).all()
-    assert (got["snr"] > cfg.snr_thresh).all()
+    assert (got["snr"] >= np.float32(cfg.snr_thresh)).all()  # FP64 S/N > theta may round to theta in FP32
