@@ -38,7 +38,7 @@ namespace {
 constexpr int kC = 1024;                 // samples (window ends) per step
 constexpr int kRing = 8192;              // ring entries, >= kC + 64 + max width
 constexpr int kGroups = kC / 64;         // 64-position groups per step and width
-constexpr int kCbuf = 512;               // LDS candidate staging records
+constexpr int kCbuf = 64;                // LDS candidate staging records per buffer
 
 struct Emitter {
   sps_cand* cbuf;       // LDS staging (null: write to global directly)
@@ -173,18 +173,32 @@ __device__ __forceinline__ int group_shift(int w) {
   return (64 - (sub & 63)) & 63;
 }
 
+// NW > 0: the number of widths is a compile-time constant (fast pass unrolled);
+// NW == 0: any number of widths.
+//
+// Step c has three phases separated by barriers:
+//   A  write P of step c into the ring; bounds for step c's centre blocks
+//   B  fast pass over step c; residuals and wave scan of step c+1; flush slot
+//      for the candidates staged during step c-1
+//   C  copy those candidates out; run pass over step c's flagged widths
+//   D  (no barrier) owner waves fold step c into their widths' summaries
+// Samples, medians and MADs are fetched one step ahead of their use.
+template <int NW>
 __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
+  const int nw = NW > 0 ? NW : A.nw;
   __shared__ uint32_t ring[kRing];
   __shared__ int32_t tlo[kMaxWidths][kGroups];
   __shared__ int32_t thi[kMaxWidths][kGroups];
   __shared__ double tden[kMaxWidths][kGroups];
   __shared__ RunSum carry[kMaxWidths];
   __shared__ RunSum wsum[kMaxWidths][4];
-  __shared__ sps_cand cbuf[kCbuf];
-  __shared__ uint32_t wtot[4];
-  __shared__ uint32_t step_mask, cbuf_n, flush_n, flush_base;
+  __shared__ sps_cand cbuf[2][kCbuf];
+  __shared__ uint32_t wtot[2][4];
+  __shared__ uint32_t step_mask, flush_n, flush_base;
+  __shared__ uint32_t cbuf_n[2];
 
-  const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+  const int tid = threadIdx.x, lane = lane_id();
+  const int wave = readfirst(tid >> 6);
   const int row = blockIdx.x / A.nseg;
   const int seg = blockIdx.x - row * A.nseg;
   const int N = A.N;
@@ -200,50 +214,75 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
   const int e_row = N - s0;  // E <= N - s0      <=> i <= N - w
   const int e_seg = s1 - s0; // E < s1 - s0 + w  <=> i < s1
 
-  if (tid < A.nw) carry[tid] = rs_empty();
-  if (tid == 0) { ring[3] = 0u; cbuf_n = 0u; }
+  // bound-table thread: (width tj, group tg)
+  const bool tthr = tid < nw * kGroups;
+  const int tj = tthr ? tid / kGroups : 0, tg = tid - tj * kGroups;
+  const double tsq = tthr ? A.sqrtw[tj] : 1.0;
+  const int tw = 1 << tj;
+  const int tk0 = s0 - group_shift(tw) - (tw - (tw >> 1));  // centre of group 0, step 0
+  auto fetch_mad = [&](int c) -> int {
+    if (!tthr) return 0;
+    const int k = ((tk0 + c * kC) >> 6) + tg;
+    return (k >= 0 && k < A.nblocks) ? madr[k] : 0;
+  };
+  // samples s0 + c*kC + 4*tid + q of step c
+  auto fetch = [&](int c, int& mk, float& f0, float& f1, float& f2, float& f3) {
+    const int t0 = s0 + c * kC + 4 * tid;
+    mk = 0; f0 = f1 = f2 = f3 = 0.f;
+    if (t0 < N) {
+      mk = medr[t0 >> 6];
+      if (vec && t0 + 3 < N) {
+        const float4 v = *reinterpret_cast<const float4*>(xr + t0);
+        f0 = v.x; f1 = v.y; f2 = v.z; f3 = v.w;
+      } else {
+        f0 = xr[t0];
+        if (t0 + 1 < N) f1 = xr[t0 + 1];
+        if (t0 + 2 < N) f2 = xr[t0 + 2];
+        if (t0 + 3 < N) f3 = xr[t0 + 3];
+      }
+    }
+  };
+  // residuals (zero past the row), local prefix and wave scan of step c
+  uint32_t p0, p1, p2, p3, incl;
+  auto prefix = [&](int c, int mk, float f0, float f1, float f2, float f3) {
+    const int t0 = s0 + c * kC + 4 * tid;
+    const int r0 = t0 < N ? __float2int_rz(f0) - mk : 0;
+    const int r1 = t0 + 1 < N ? __float2int_rz(f1) - mk : 0;
+    const int r2 = t0 + 2 < N ? __float2int_rz(f2) - mk : 0;
+    const int r3 = t0 + 3 < N ? __float2int_rz(f3) - mk : 0;
+    p0 = (uint32_t)r0; p1 = p0 + (uint32_t)r1; p2 = p1 + (uint32_t)r2; p3 = p2 + (uint32_t)r3;
+    incl = (uint32_t)wave_scan_incl((int)p3);
+    if (lane == 63) wtot[c & 1][wave] = incl;
+  };
+
+  int nmk, cur_mad = fetch_mad(0), next_mad = 0;
+  float nf0, nf1, nf2, nf3;
+  fetch(0, nmk, nf0, nf1, nf2, nf3);
+  prefix(0, nmk, nf0, nf1, nf2, nf3);
+  if (nsteps > 1) fetch(1, nmk, nf0, nf1, nf2, nf3);
+  if (tid < nw) carry[tid] = rs_empty();
+  if (tid == 0) { cbuf_n[0] = 0u; cbuf_n[1] = 0u; }
   uint32_t carryP = 0;  // P at the step's first sample
   __syncthreads();
 
   for (int c = 0; c < nsteps; ++c) {
     const int cC = c * kC;
-    // residuals of samples s0 + cC + 4*tid + q and their local prefix
-    const int t0 = s0 + cC + 4 * tid;
-    int r0 = 0, r1 = 0, r2 = 0, r3 = 0;
-    if (t0 < N) {
-      const int mk = medr[t0 >> 6];
-      if (vec && t0 + 3 < N) {
-        const float4 v = *reinterpret_cast<const float4*>(xr + t0);
-        r0 = __float2int_rz(v.x) - mk; r1 = __float2int_rz(v.y) - mk;
-        r2 = __float2int_rz(v.z) - mk; r3 = __float2int_rz(v.w) - mk;
-      } else {
-        r0 = __float2int_rz(xr[t0]) - mk;
-        if (t0 + 1 < N) r1 = __float2int_rz(xr[t0 + 1]) - mk;
-        if (t0 + 2 < N) r2 = __float2int_rz(xr[t0 + 2]) - mk;
-        if (t0 + 3 < N) r3 = __float2int_rz(xr[t0 + 3]) - mk;
-      }
+    const int buf = c & 1;
+    // ---- A: ring and bounds of step c
+    {
+      uint32_t woff = 0;
+      for (int v = 0; v < wave; ++v) woff += wtot[buf][v];
+      const uint32_t tot = wtot[buf][0] + wtot[buf][1] + wtot[buf][2] + wtot[buf][3];
+      // P[E] = sum of r over the segment's first E samples; thread tid owns
+      // E = cC + 4*tid + q, so every 64 consecutive E of a wave row are one group
+      const uint32_t pb = carryP + woff + incl - p3;
+      *reinterpret_cast<uint4*>(&ring[(cC + 4 * tid) & (kRing - 1)]) = make_uint4(pb, pb + p0, pb + p1, pb + p2);
+      carryP += tot;
     }
-    const uint32_t p0 = (uint32_t)r0, p1 = p0 + (uint32_t)r1, p2 = p1 + (uint32_t)r2, p3 = p2 + (uint32_t)r3;
-    const uint32_t incl = (uint32_t)wave_scan_incl((int)p3);
-    if (lane == 63) wtot[wave] = incl;
-    __syncthreads();  // B1: wave totals; last step's emissions are complete
-
-    uint32_t woff = 0;
-    for (int v = 0; v < wave; ++v) woff += wtot[v];
-    const uint32_t tot = wtot[0] + wtot[1] + wtot[2] + wtot[3];
-    const uint32_t pb = carryP + woff + incl - p3;
-    *reinterpret_cast<uint4*>(&ring[(cC + 4 * tid + 4) & (kRing - 1)]) =
-        make_uint4(pb + p0, pb + p1, pb + p2, pb + p3);
-    carryP += tot;
-    // integer bounds and denominators: one per (width, group)
-    if (tid < A.nw * kGroups) {
-      const int j = tid / kGroups, g = tid - j * kGroups;
-      const int w = 1 << j, sub = w - (w >> 1);
-      const int k = ((s0 + cC - group_shift(w) - sub) >> 6) + g;
-      const int madv = (k >= 0 && k < A.nblocks) ? madr[k] : 0;
-      const double den = (kMadToSigma * (double)madv) * A.sqrtw[j];
+    if (tthr) {
+      const double den = (kMadToSigma * (double)cur_mad) * tsq;
       int lo = INT_MAX, hi = INT_MAX;
-      if (madv > 0) {
+      if (cur_mad > 0) {
         const double tt = A.theta * den;
         if (tt < 2147483648.0) {
           lo = (int)(floor(tt) - 1.0);
@@ -251,66 +290,81 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
           hi = hd >= 2147483647.0 ? INT_MAX : (int)hd;
         }
       }
-      tlo[j][g] = lo;
-      thi[j][g] = hi;
-      tden[j][g] = madv > 0 ? den : 1.0;
+      tlo[tj][tg] = lo;
+      thi[tj][tg] = hi;
+      tden[tj][tg] = cur_mad > 0 ? den : 1.0;
     }
+    if (c + 1 < nsteps) next_mad = fetch_mad(c + 1);
+    if (tid == 0) step_mask = 0u;
+    __syncthreads();  // BA
+
+    // ---- B: flush slot for step c-1's candidates; fast pass; prefix of step c+1
+    uint32_t fl_n = 0, fl_base = 0;
     if (tid == 0) {
-      step_mask = 0u;
-      const uint32_t n = min(cbuf_n, (uint32_t)kCbuf);
-      flush_n = n;
-      flush_base = n ? atomicAdd(A.ncand, n) : 0u;
-      cbuf_n = 0u;
+      fl_n = min(cbuf_n[buf ^ 1], (uint32_t)kCbuf);
+      cbuf_n[buf ^ 1] = 0u;
+      if (fl_n) fl_base = atomicAdd(A.ncand, fl_n);
     }
-    __syncthreads();  // B2: ring, bounds, flush slot
-
-    {  // flush the previous step's staged candidates
-      const uint32_t n = flush_n, base = flush_base;
-      for (uint32_t i = tid; i < n; i += 256)
-        if (base + i < A.cap) A.cands[base + i] = cbuf[i];
-    }
-
-    // fast pass: does any position of this step pass a width's bound?
     {
+      uint32_t flagged = 0u;
       int cur_shift = -1;
       uint32_t pe[4] = {0u, 0u, 0u, 0u};
-      for (int j = 0; j < A.nw; ++j) {
+#pragma unroll
+      for (int j = 0; j < (NW > 0 ? NW : kMaxWidths); ++j) {
+        if (NW == 0 && j >= nw) break;
         const int w = 1 << j, sh = group_shift(w);
         const int eg = cC - sh + 256 * wave;
         if (sh != cur_shift) {
           cur_shift = sh;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) pe[q] = ring[(eg + 64 * q + lane + 3) & (kRing - 1)];
+          for (int q = 0; q < 4; ++q) pe[q] = ring[(eg + 64 * q + lane) & (kRing - 1)];
         }
         const int vhi = min(e_seg + w - 1, e_row);
+        const bool allv = eg >= w && eg + 255 <= vhi;  // every position of this wave valid
+        const int4 T4 = *reinterpret_cast<const int4*>(&tlo[j][4 * wave]);
         uint64_t acc = 0ull;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int e0 = eg + 64 * q;
-          const int S = (int)(pe[q] - ring[(e0 + lane - w + 3) & (kRing - 1)]);
-          const int T = tlo[j][4 * wave + q];
-          acc |= ballot(S > T) & lane_range(w - e0, vhi - e0);
+          // P[E - w]: when E - w is 64-aligned the group never wraps the ring
+          const uint32_t pw = ((e0 - w) & 63) == 0 ? ring[((e0 - w) & (kRing - 1)) + lane]
+                                                   : ring[(e0 - w + lane) & (kRing - 1)];
+          const int S = (int)(pe[q] - pw);
+          const int T = q == 0 ? T4.x : q == 1 ? T4.y : q == 2 ? T4.z : T4.w;
+          const uint64_t hit = ballot(S > T);
+          acc |= allv ? hit : (hit & lane_range(w - e0, vhi - e0));
         }
-        if (acc && lane == 0) atomicOr(&step_mask, 1u << j);
+        if (acc) flagged |= 1u << j;
       }
+      if (flagged && lane == 0) atomicOr(&step_mask, flagged);
     }
-    __syncthreads();  // B3: step_mask complete; flush copies done
+    if (c + 1 < nsteps) {
+      prefix(c + 1, nmk, nf0, nf1, nf2, nf3);
+      if (c + 2 < nsteps) fetch(c + 2, nmk, nf0, nf1, nf2, nf3);
+    }
+    if (tid == 0) { flush_n = fl_n; flush_base = fl_base; }
+    __syncthreads();  // BB
 
-    // run pass for widths with candidates in this step
+    // ---- C: copy out step c-1's candidates; run pass
+    {
+      const uint32_t n = flush_n, base = flush_base;
+      for (uint32_t i = tid; i < n; i += 256)
+        if (base + i < A.cap) A.cands[base + i] = cbuf[buf ^ 1][i];
+    }
     const uint32_t smask = step_mask;
-    for (int j = 0; j < A.nw; ++j) {
+    for (int j = 0; j < nw; ++j) {
       if (!((smask >> j) & 1u)) continue;
       const int w = 1 << j, sh = group_shift(w);
       const int eg = cC - sh + 256 * wave;
       const int vhi = min(e_seg + w - 1, e_row);
-      const Emitter em{cbuf, &cbuf_n, A.cands, A.ncand, A.cap, dm, (uint32_t)w, lane == 0};
+      const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, lane == 0};
       RunSum acc = rs_empty();
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int e0 = eg + 64 * q, g = 4 * wave + q;
         const int e = e0 + lane;
-        const int S = (int)(ring[(e + 3) & (kRing - 1)] - ring[(e - w + 3) & (kRing - 1)]);
-        const int lo = tlo[j][g], hi = thi[j][g];
+        const int S = (int)(ring[e & (kRing - 1)] - ring[(e - w) & (kRing - 1)]);
+        const int lo = readfirst(tlo[j][g]), hi = readfirst(thi[j][g]);
         const double d = tden[j][g];
         const bool above = S > lo && ((S >= hi && hi != INT_MAX) || (double)S / d > A.theta);
         const uint64_t V = lane_range(w - e0, vhi - e0);
@@ -320,12 +374,13 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
       }
       if (lane == 0) wsum[j][wave] = acc;
     }
-    __syncthreads();  // B4: wave summaries
+    cur_mad = next_mad;
+    __syncthreads();  // BC
 
-    // width j is owned by wave j % 4: fold the step into its running summary
-    for (int j = wave; j < A.nw; j += 4) {
+    // ---- D: width j is owned by wave j % 4
+    for (int j = wave; j < nw; j += 4) {
       const int w = 1 << j, sh = group_shift(w);
-      const Emitter em{cbuf, &cbuf_n, A.cands, A.ncand, A.cap, dm, (uint32_t)w, lane == 0};
+      const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, lane == 0};
       RunSum cj = carry[j];
       bool dirty = false;
       if ((smask >> j) & 1u) {
@@ -351,21 +406,22 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
   }
 
   __syncthreads();
-  for (int j = wave; j < A.nw; j += 4) {
+  const int lb = (nsteps - 1) & 1;  // staging buffer of the last step
+  for (int j = wave; j < nw; j += 4) {
     const RunSum cj = carry[j];
-    const Emitter em{cbuf, &cbuf_n, A.cands, A.ncand, A.cap, dm, (uint32_t)(1 << j), lane == 0};
+    const Emitter em{cbuf[lb], &cbuf_n[lb], A.cands, A.ncand, A.cap, dm, (uint32_t)(1 << j), lane == 0};
     if (A.nseg == 1) rs_close(cj, em);
-    else if (lane == 0) A.frag[((int64_t)row * A.nw + j) * A.nseg + seg] = cj;
+    else if (lane == 0) A.frag[((int64_t)row * nw + j) * A.nseg + seg] = cj;
   }
   __syncthreads();
   if (tid == 0) {
-    const uint32_t n = min(cbuf_n, (uint32_t)kCbuf);
+    const uint32_t n = min(cbuf_n[lb], (uint32_t)kCbuf);
     flush_n = n;
     flush_base = n ? atomicAdd(A.ncand, n) : 0u;
   }
   __syncthreads();
   for (uint32_t i = tid; i < flush_n; i += 256)
-    if (flush_base + i < A.cap) A.cands[flush_base + i] = cbuf[i];
+    if (flush_base + i < A.cap) A.cands[flush_base + i] = cbuf[lb][i];
 }
 
 // Stitch the segment summaries of each (row, width) in order.
@@ -391,7 +447,12 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 hipError_t launch_detect(const DetectArgs& a, hipStream_t s) {
   const int64_t grid = (int64_t)a.rows * a.nseg;
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_detect, dim3((unsigned)grid), dim3(256), 0, s, a);
+  if (a.nw == 13)
+    hipLaunchKernelGGL(k_detect<13>, dim3((unsigned)grid), dim3(256), 0, s, a);
+  else if (a.nw == 7)
+    hipLaunchKernelGGL(k_detect<7>, dim3((unsigned)grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_detect<0>, dim3((unsigned)grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -233,6 +233,32 @@ __device__ void chain_init(Chain<NB>& c, int lo, int hi) {
   if (!full_query(c, below)) exact_block(c, lo, hi);
 }
 
+// Rare path: answer from the whole histogram, recentre it when the quantiles
+// near its edges, or fall back to the exact select. Kept out of line so the
+// unrolled block loop stays small.
+template <int NB>
+__device__ void slow_block(Chain<NB>& c, int lo, int hi) {
+  // #{x < base} from the exact count below the old median
+  const int im = c.m - c.base;
+  int s = 0;
+  for (int i0 = 0; i0 < im; i0 += 64) {
+    const int i = i0 + c.lane;
+    s += i < im ? hist_get(c.H, i) : 0;
+  }
+  const int below = c.cm - wave_sum_u(s);
+  if (full_query(c, below)) {
+    // keep the local queries' windows inside the histogram: recentre near an edge
+    if (c.m - c.d - 96 < c.base || c.m + c.d + 97 > c.base + NB) {
+      if (c.d < NB / 2 - 128) {
+        const int b2 = rebuild(c, lo, hi, c.m - NB / 2);
+        c.raw = !full_query(c, b2);
+      }
+    }
+    return;
+  }
+  exact_block(c, lo, hi);
+}
+
 template <int NB>
 __device__ __forceinline__ void chain_step(Chain<NB>& c, int lo, int hi, bool a_ok, int av, bool b_ok, int bv) {
   c.n += popc(ballot(a_ok)) - popc(ballot(b_ok));
@@ -249,25 +275,7 @@ __device__ __forceinline__ void chain_step(Chain<NB>& c, int lo, int hi, bool a_
   c.cU += popc(ballot(a_ok && av < pU)) - popc(ballot(b_ok && bv < pU));
   wave_lds_fence();
   if (fast_query(c)) return;
-  // #{x < base} from the exact count below the old median
-  const int im = c.m - c.base;
-  int s = 0;
-  for (int i0 = 0; i0 < im; i0 += 64) {
-    const int i = i0 + c.lane;
-    s += i < im ? hist_get(c.H, i) : 0;
-  }
-  const int below = c.cm - wave_sum_u(s);
-  if (full_query(c, below)) {
-    // keep the fast path's windows inside the histogram: recentre if close to an edge
-    if (c.m - c.d - 96 < c.base || c.m + c.d + 97 > c.base + NB) {
-      if (c.d < NB / 2 - 128) {
-        const int b2 = rebuild(c, lo, hi, c.m - NB / 2);
-        c.raw = !full_query(c, b2);
-      }
-    }
-    return;
-  }
-  exact_block(c, lo, hi);
+  slow_block(c, lo, hi);
 }
 
 // WPG chains (waves) per workgroup; LDS = WPG * NB * 2 bytes.
