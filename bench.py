@@ -66,11 +66,29 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=[1, 2])
     ap.add_argument("--cpu-rows", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="search", choices=["search", "copy"],
+                    help="copy: time a plain device-to-device copy of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the search shards by DM rows with no exchange, "
               "and this build measures one GPU's share (got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.mode == "copy":
+        import torch
+        n = 1 << 28  # 2^28 float32 = 1 GiB read + 1 GiB written per copy
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "ms": dt * 1e3,
+                          "GBps_read_plus_write": 8 * n / dt / 1e9}))
+        return
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -27,6 +27,7 @@
 // wave per width), steps and, through the fix-up kernel, segments.
 // Candidates are staged in LDS and flushed with one global atomic per step.
 #include <climits>
+#include <type_traits>
 
 #include "sps_internal.h"
 #include "sps_wave.h"
@@ -306,36 +307,45 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
       if (fl_n) fl_base = atomicAdd(A.ncand, fl_n);
     }
     {
+      // interior step: every position of every width is valid, no masks needed
+      const bool clean = cC - 64 >= A.maxw && cC + kC - 1 <= min(e_seg, e_row - A.maxw);
       uint32_t flagged = 0u;
-      int cur_shift = -1;
-      uint32_t pe[4] = {0u, 0u, 0u, 0u};
+      auto fast = [&](auto CLEAN) {
+        int cur_shift = -1;
+        uint32_t pe[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-      for (int j = 0; j < (NW > 0 ? NW : kMaxWidths); ++j) {
-        if (NW == 0 && j >= nw) break;
-        const int w = 1 << j, sh = group_shift(w);
-        const int eg = cC - sh + 256 * wave;
-        if (sh != cur_shift) {
-          cur_shift = sh;
+        for (int j = 0; j < (NW > 0 ? NW : kMaxWidths); ++j) {
+          if (NW == 0 && j >= nw) break;
+          const int w = 1 << j, sh = group_shift(w);
+          const int eg = cC - sh + 256 * wave;
+          if (sh != cur_shift) {
+            cur_shift = sh;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) pe[q] = ring[(eg + 64 * q + lane) & (kRing - 1)];
+            for (int q = 0; q < 4; ++q) pe[q] = ring[(eg + 64 * q + lane) & (kRing - 1)];
+          }
+          const int4 T4 = *reinterpret_cast<const int4*>(&tlo[j][4 * wave]);
+          uint64_t acc = 0ull;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int e0 = eg + 64 * q;
+            // P[E - w]: when E - w is 64-aligned the group never wraps the ring
+            const uint32_t pw = ((e0 - w) & 63) == 0 ? ring[((e0 - w) & (kRing - 1)) + lane]
+                                                     : ring[(e0 - w + lane) & (kRing - 1)];
+            const int S = (int)(pe[q] - pw);
+            const int T = q == 0 ? T4.x : q == 1 ? T4.y : q == 2 ? T4.z : T4.w;
+            const uint64_t hit = ballot(S > T);
+            if (CLEAN) {
+              acc |= hit;
+            } else {
+              const int vhi = min(e_seg + w - 1, e_row);
+              acc |= hit & lane_range(w - e0, vhi - e0);
+            }
+          }
+          flagged |= acc ? (1u << j) : 0u;
         }
-        const int vhi = min(e_seg + w - 1, e_row);
-        const bool allv = eg >= w && eg + 255 <= vhi;  // every position of this wave valid
-        const int4 T4 = *reinterpret_cast<const int4*>(&tlo[j][4 * wave]);
-        uint64_t acc = 0ull;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e0 = eg + 64 * q;
-          // P[E - w]: when E - w is 64-aligned the group never wraps the ring
-          const uint32_t pw = ((e0 - w) & 63) == 0 ? ring[((e0 - w) & (kRing - 1)) + lane]
-                                                   : ring[(e0 - w + lane) & (kRing - 1)];
-          const int S = (int)(pe[q] - pw);
-          const int T = q == 0 ? T4.x : q == 1 ? T4.y : q == 2 ? T4.z : T4.w;
-          const uint64_t hit = ballot(S > T);
-          acc |= allv ? hit : (hit & lane_range(w - e0, vhi - e0));
-        }
-        if (acc) flagged |= 1u << j;
-      }
+      };
+      if (clean) fast(std::true_type{});
+      else fast(std::false_type{});
       if (flagged && lane == 0) atomicOr(&step_mask, flagged);
     }
     if (c + 1 < nsteps) {

@@ -274,14 +274,15 @@ __device__ __forceinline__ void chain_step(Chain<NB>& c, int lo, int hi, bool a_
   c.cL += popc(ballot(a_ok && av < pL)) - popc(ballot(b_ok && bv < pL));
   c.cU += popc(ballot(a_ok && av < pU)) - popc(ballot(b_ok && bv < pU));
   wave_lds_fence();
-  if (fast_query(c)) return;
-  slow_block(c, lo, hi);
+  if (!fast_query(c)) slow_block(c, lo, hi);
 }
 
 // WPG chains (waves) per workgroup; LDS = WPG * NB * 2 bytes.
 template <int NB, int WPG>
 __global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
   __shared__ uint32_t hist[WPG][NB / 2];
+  // wave index kept in a VGPR: the chain state then stays on the vector unit,
+  // which measures faster than moving its bookkeeping to the shared scalar unit
   const int wave = threadIdx.x >> 6;
   const int lane = lane_id();
   const int chain = blockIdx.x * WPG + wave;

@@ -13,7 +13,8 @@ __device__ __forceinline__ int lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
 
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+// Lanes where p holds; compiles to the compare's own lane mask.
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ int popc(uint64_t m) { return __popcll(m); }
 
@@ -71,12 +72,13 @@ __device__ __forceinline__ int wave_max_u(int v) {
 __device__ __forceinline__ int wave_sum_u(int v) { return readlane(wave_scan_incl(v), 63); }
 
 // Lanes lo..hi (inclusive, clipped to 0..63) as a mask; empty if lo > hi.
+// Branch-free (selects only).
 __device__ __forceinline__ uint64_t lane_range(int lo, int hi) {
-  lo = lo < 0 ? 0 : lo;
-  hi = hi > 63 ? 63 : hi;
-  if (lo > hi) return 0ull;
-  const uint64_t upto = hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull);
-  return upto & (~0ull << lo);
+  const int l = lo < 0 ? 0 : (lo > 63 ? 63 : lo);
+  const int h = hi > 63 ? 63 : (hi < 0 ? 0 : hi);
+  const uint64_t upto = (2ull << h) - 1ull;  // h = 63: 2^64 wraps to 0, minus 1 = all lanes
+  const uint64_t m = upto & (~0ull << l);
+  return (lo > hi || hi < 0 || lo > 63) ? 0ull : m;
 }
 
 }  // namespace sps
