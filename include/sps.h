@@ -150,6 +150,40 @@ int sps_plan_get(const sps_plan* plan, int attr, int64_t* value);
 #define SPS_NSTAGES 4
 int sps_timing_read(sps_plan* plan, double* ms_out, int64_t* nsearch);
 
+/*
+ * Streaming: one long observation searched gulp by gulp, exactly as if the
+ * gulps were one block (chunks overlap "to preserve signal continuity",
+ * Section III-B; double-buffered chunk reads, Sections IV-C and V-C). The
+ * carried state stays on the device: per row the last max(baseline_len,
+ * max_width) samples (rounded up to 1024) with their block medians/MADs, and
+ * per (row, width) a summary of the run still open at the end of the last
+ * gulp (20 KiB + 520 B per row at baseline 16384).
+ *
+ * sps_stream_create: `plan` gives the gulp shape (ndm x nsamp, nsamp a
+ *   multiple of 64) and parameters; it must outlive the stream, and the
+ *   stream must not run concurrently with another use of the plan.
+ * sps_stream_push: search one gulp (device FP32 [ndm][nsamp]); candidates are
+ *   those whose runs ended during this gulp, with `sample` relative to the
+ *   gulp's first sample (negative: the boxcar started in an earlier gulp).
+ *   *gulp_offset (host, may be NULL) receives the global index of the gulp's
+ *   first sample. d_ncand/d_cands as in sps_search. Asynchronous.
+ * sps_stream_flush: end of observation: emits the runs still open, `sample`
+ *   relative to the sample after the last gulp (*end_offset = samples
+ *   pushed). The stream can then be reused only after restore.
+ * sps_stream_state_size / save / restore: checkpoint the carried state to
+ *   host memory and back (host-synchronous on `stream`); a restored stream
+ *   continues exactly as the saved one would have.
+ */
+typedef struct sps_stream sps_stream;
+int sps_stream_create(sps_plan* plan, sps_stream** out);
+int sps_stream_push(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand,
+                    int64_t* gulp_offset);
+int sps_stream_flush(sps_stream* s, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand, int64_t* end_offset);
+int sps_stream_state_size(const sps_stream* s, uint64_t* bytes);
+int sps_stream_save(sps_stream* s, hipStream_t stream, void* host_buf, uint64_t bytes);
+int sps_stream_restore(sps_stream* s, hipStream_t stream, const void* host_buf, uint64_t bytes);
+void sps_stream_destroy(sps_stream* s);
+
 /* Last error code of the calling thread, and a static text for a code. */
 int sps_last_error(void);
 const char* sps_error_string(int code);

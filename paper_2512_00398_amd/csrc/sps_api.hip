@@ -54,35 +54,42 @@ int ok() {
 
 constexpr int kDetectStep = 1024;
 
-int auto_stats_seg(const sps_plan* p) {
-  if (p->stats_seg > 0) return p->stats_seg;
+// Blocks per baseline chain for `nb` blocks per row (tuning only).
+int stats_seg_for(const sps_plan* p, int64_t nb) {
+  if (p->stats_seg > 0) return (int)std::min<int64_t>(p->stats_seg, std::max<int64_t>(nb, 1));
   // ~10k chains fill 256 CUs x ~20 resident waves twice over; keep each
   // chain >= 4 windows long so the warm-up recount stays a small overhead.
   const int64_t want_chains = 10240;
   int64_t per_row = (want_chains + p->ndm - 1) / p->ndm;
   if (per_row < 1) per_row = 1;
-  int64_t seg = (p->nblocks + per_row - 1) / per_row;
+  int64_t seg = (nb + per_row - 1) / per_row;
   const int64_t min_seg = std::max<int64_t>(64, (4LL * p->baseline_len + 63) / 64);
   if (seg < min_seg) seg = min_seg;
-  if (seg > p->nblocks) seg = p->nblocks;
+  if (seg > nb) seg = nb;
   if (seg < 1) seg = 1;
   return (int)seg;
 }
 
-int auto_detect_seg(const sps_plan* p) {
+int auto_stats_seg(const sps_plan* p) { return stats_seg_for(p, p->nblocks); }
+
+// Positions per detection segment for rows of `npos` positions (tuning only).
+int detect_seg_for(const sps_plan* p, int64_t npos) {
   int64_t seg = p->detect_seg;
   if (seg <= 0) {
     // ~4096 workgroups; each segment >= 4 x max_width so the halo stays small
-    const int64_t total = (int64_t)p->ndm * p->nsamp;
+    const int64_t total = (int64_t)p->ndm * npos;
     seg = total / 4096;
     seg = std::max<int64_t>(seg, 4LL * p->max_width);
   }
   seg = ((seg + kDetectStep - 1) / kDetectStep) * kDetectStep;
   if (seg < kDetectStep) seg = kDetectStep;
-  const int64_t nmax = ((int64_t)p->nsamp + kDetectStep - 1) / kDetectStep * kDetectStep;
+  const int64_t nmax = (npos + kDetectStep - 1) / kDetectStep * kDetectStep;
   if (seg > nmax) seg = nmax;
+  if (seg < kDetectStep) seg = kDetectStep;
   return (int)seg;
 }
+
+int auto_detect_seg(const sps_plan* p) { return detect_seg_for(p, p->nsamp); }
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -318,12 +325,17 @@ static int launch_stats(sps_plan* p, const float* d_series, hipStream_t stream, 
   sps::StatsArgs a;
   a.x = d_series;
   a.ld = p->nsamp;
+  a.hist = nullptr;
+  a.ldh = 0;
+  a.Hx = 0;
   a.N = p->nsamp;
   a.L = p->baseline_len;
   a.nblocks = p->nblocks;
+  a.kb_first = 0;
   a.seg_blocks = auto_stats_seg(p);
   a.nseg = (p->nblocks + a.seg_blocks - 1) / a.seg_blocks;
   a.nchains = p->ndm * a.nseg;
+  a.tmin = nullptr;
   a.med = d_median;
   a.mad = d_mad;
   if (sps::launch_block_stats(a, p->hist_bins, stream) != hipSuccess) return fail(SPS_ERR_HIP);
@@ -345,6 +357,14 @@ int sps_search(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand*
   hipEvent_t e2 = mark(p, stream);
   d.x = d_series;
   d.ld = p->nsamp;
+  d.hist = nullptr;
+  d.ldh = 0;
+  d.Hx = 0;
+  d.seg_base = 0;
+  d.e_first = 0;
+  d.tmin = nullptr;
+  d.sample_offset = 0;
+  d.keep_edges = 0;
   d.N = p->nsamp;
   d.nblocks = p->nblocks;
   d.nw = p->nw;
@@ -374,6 +394,299 @@ int sps_search(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand*
 int sps_search_plain(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand) {
   (void)p; (void)d_series; (void)stream; (void)d_cands; (void)d_ncand;
   return fail(SPS_ERR_INVALID_ARG);  // provided by the per-stage path (sps_plain.hip)
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Streaming: gulp after gulp of one observation, the carried state on device.
+
+struct sps_stream {
+  sps_plan* plan;       // borrowed: gulp shape and tuning
+  int32_t Hx;           // history samples kept per row (multiple of 1024)
+  int32_t Hb;           // Hx / 64
+  int32_t nbv;          // virtual blocks per row: Hb + nsamp / 64
+  int32_t Nv;           // virtual samples per row: Hx + nsamp
+  int32_t seg_base;     // first detection segment start (virtual)
+  int32_t seg_len, nseg;
+  int cur;              // which of the two history buffers is current
+  float* hist[2];       // [ndm][Hx]
+  int32_t* med[2];      // [ndm][nbv]
+  int32_t* mad[2];
+  sps::RunSum* carry;   // [ndm][nw]
+  sps::RunSum* frag;    // [ndm][nw][nseg]
+  int32_t* tmin;        // device: virtual index of the stream's first sample (clamped at 0)
+  int64_t pushed;       // samples pushed so far
+};
+
+namespace {
+
+struct StreamHeader {
+  uint64_t magic;
+  int64_t pushed;
+  int32_t ndm, nsamp, Hx, nw, max_width, baseline_len;
+  int32_t tmin;
+  int32_t pad;
+};
+constexpr uint64_t kStreamMagic = 0x5350535354524D31ull;  // "SPSSTRM1"
+
+uint64_t stream_state_bytes(const sps_stream* s) {
+  const sps_plan* p = s->plan;
+  return sizeof(StreamHeader) + (uint64_t)p->ndm * s->Hx * sizeof(float) +
+         2ull * p->ndm * s->Hb * sizeof(int32_t) + (uint64_t)p->ndm * p->nw * sizeof(sps::RunSum);
+}
+
+sps::StreamArgs stream_args(sps_stream* s, const float* d_gulp, sps_cand* d_cands, uint32_t* d_ncand) {
+  sps_plan* p = s->plan;
+  sps::StreamArgs a;
+  a.rows = p->ndm;
+  a.nw = p->nw;
+  a.nseg = s->nseg;
+  a.Hx = s->Hx;
+  a.Hb = s->Hb;
+  a.ngulp = p->nsamp;
+  a.nbv = s->nbv;
+  a.frag = s->frag;
+  a.carry = s->carry;
+  a.gulp = d_gulp;
+  a.hist_in = s->hist[s->cur];
+  a.hist_out = s->hist[s->cur ^ 1];
+  a.med_in = s->med[s->cur];
+  a.mad_in = s->mad[s->cur];
+  a.med_out = s->med[s->cur ^ 1];
+  a.mad_out = s->mad[s->cur ^ 1];
+  a.tmin = s->tmin;
+  a.row_offset = 0;
+  a.cands = d_cands;
+  a.ncand = d_ncand;
+  a.cap = (uint32_t)p->max_cands;
+  return a;
+}
+
+void stream_free(sps_stream* s) {
+  if (!s) return;
+  for (int i = 0; i < 2; ++i) {
+    if (s->hist[i]) (void)hipFree(s->hist[i]);
+    if (s->med[i]) (void)hipFree(s->med[i]);
+    if (s->mad[i]) (void)hipFree(s->mad[i]);
+  }
+  if (s->carry) (void)hipFree(s->carry);
+  if (s->frag) (void)hipFree(s->frag);
+  if (s->tmin) (void)hipFree(s->tmin);
+  delete s;
+}
+
+// Zero the carried state and put the stream start at the first sample of
+// the next push (host-synchronous).
+int stream_reset(sps_stream* s) {
+  const sps_plan* p = s->plan;
+  for (int i = 0; i < 2; ++i) {
+    if (hipMemset(s->hist[i], 0, (size_t)p->ndm * s->Hx * sizeof(float)) != hipSuccess) return SPS_ERR_HIP;
+    if (hipMemset(s->med[i], 0, (size_t)p->ndm * s->nbv * sizeof(int32_t)) != hipSuccess) return SPS_ERR_HIP;
+    if (hipMemset(s->mad[i], 0, (size_t)p->ndm * s->nbv * sizeof(int32_t)) != hipSuccess) return SPS_ERR_HIP;
+  }
+  if (hipMemset(s->carry, 0, (size_t)p->ndm * p->nw * sizeof(sps::RunSum)) != hipSuccess) return SPS_ERR_HIP;
+  const int32_t t0 = s->Hx;
+  if (hipMemcpy(s->tmin, &t0, sizeof(t0), hipMemcpyHostToDevice) != hipSuccess) return SPS_ERR_HIP;
+  s->cur = 0;
+  s->pushed = 0;
+  return SPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sps_stream_create(sps_plan* p, sps_stream** out) {
+  if (!p || !out) return fail(SPS_ERR_INVALID_ARG);
+  *out = nullptr;
+  if (p->nsamp % sps::kStride != 0) return fail(SPS_ERR_INVALID_ARG);  // gulps must hold whole blocks
+  sps_stream* s = new (std::nothrow) sps_stream;
+  if (!s) return fail(SPS_ERR_OOM);
+  std::memset(s, 0, sizeof(*s));
+  s->plan = p;
+  const int64_t need = std::max<int64_t>(p->baseline_len, p->max_width);
+  s->Hx = (int32_t)((need + kDetectStep - 1) / kDetectStep * kDetectStep);
+  s->Hb = s->Hx / sps::kStride;
+  s->nbv = s->Hb + p->nsamp / sps::kStride;
+  if ((int64_t)s->Hx + p->nsamp > (int64_t)INT32_MAX - 8192) {
+    delete s;
+    return fail(SPS_ERR_INVALID_ARG);
+  }
+  s->Nv = s->Hx + p->nsamp;
+  // positions of a push are those whose window ends inside the gulp
+  int64_t first = (int64_t)s->Hx + 1 - p->max_width;
+  if (first < 0) first = 0;
+  s->seg_base = (int32_t)(first / kDetectStep * kDetectStep);
+  s->seg_len = detect_seg_for(p, s->Nv - s->seg_base);
+  s->nseg = (s->Nv - s->seg_base + s->seg_len - 1) / s->seg_len;
+  bool okm = true;
+  for (int i = 0; i < 2 && okm; ++i) {
+    okm = hipMalloc(&s->hist[i], (size_t)p->ndm * s->Hx * sizeof(float)) == hipSuccess &&
+          hipMalloc(&s->med[i], (size_t)p->ndm * s->nbv * sizeof(int32_t)) == hipSuccess &&
+          hipMalloc(&s->mad[i], (size_t)p->ndm * s->nbv * sizeof(int32_t)) == hipSuccess;
+  }
+  okm = okm && hipMalloc(&s->carry, (size_t)p->ndm * p->nw * sizeof(sps::RunSum)) == hipSuccess &&
+        hipMalloc(&s->frag, (size_t)p->ndm * p->nw * s->nseg * sizeof(sps::RunSum)) == hipSuccess &&
+        hipMalloc(&s->tmin, sizeof(int32_t)) == hipSuccess;
+  if (!okm) {
+    (void)hipGetLastError();
+    stream_free(s);
+    return fail(SPS_ERR_OOM);
+  }
+  if (stream_reset(s) != SPS_OK) {
+    stream_free(s);
+    return fail(SPS_ERR_HIP);
+  }
+  *out = s;
+  return ok();
+}
+
+void sps_stream_destroy(sps_stream* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  stream_free(s);
+}
+
+int sps_stream_push(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand,
+                    int64_t* gulp_offset) {
+  if (!s || !d_gulp || !d_ncand || (!d_cands && s->plan->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+  sps_plan* p = s->plan;
+  const int c = s->cur;
+  hipEvent_t e0 = mark(p, stream);
+  if (sps::launch_zero_u32(d_ncand, 1, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  hipEvent_t e1 = mark(p, stream);
+  sps::StatsArgs a;
+  a.x = d_gulp;
+  a.ld = p->nsamp;
+  a.hist = s->hist[c];
+  a.ldh = s->Hx;
+  a.Hx = s->Hx;
+  a.N = s->Nv;
+  a.L = p->baseline_len;
+  a.nblocks = s->nbv;
+  a.kb_first = s->Hb;
+  a.seg_blocks = stats_seg_for(p, s->nbv - s->Hb);
+  a.nseg = (s->nbv - s->Hb + a.seg_blocks - 1) / a.seg_blocks;
+  a.nchains = p->ndm * a.nseg;
+  a.tmin = s->tmin;
+  a.med = s->med[c];
+  a.mad = s->mad[c];
+  if (sps::launch_block_stats(a, p->hist_bins, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  hipEvent_t e2 = mark(p, stream);
+  sps::DetectArgs d;
+  d.x = d_gulp;
+  d.ld = p->nsamp;
+  d.hist = s->hist[c];
+  d.ldh = s->Hx;
+  d.Hx = s->Hx;
+  d.N = s->Nv;
+  d.nblocks = s->nbv;
+  d.nw = p->nw;
+  d.maxw = p->max_width;
+  d.med = s->med[c];
+  d.mad = s->mad[c];
+  d.theta = (double)p->thresh;
+  for (int j = 0; j < sps::kMaxWidths; ++j) d.sqrtw[j] = j < p->nw ? p->sqrtw[j] : 0.0;
+  d.seg_base = s->seg_base;
+  d.seg_len = s->seg_len;
+  d.nseg = s->nseg;
+  d.rows = p->ndm;
+  d.e_first = s->Hx + 1;
+  d.tmin = s->tmin;
+  d.sample_offset = s->Hx;
+  d.keep_edges = 1;
+  d.row_offset = 0;
+  d.cands = d_cands;
+  d.ncand = d_ncand;
+  d.cap = (uint32_t)p->max_cands;
+  d.frag = s->frag;
+  if (sps::launch_detect(d, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  hipEvent_t e3 = mark(p, stream);
+  const sps::StreamArgs sa = stream_args(s, d_gulp, d_cands, d_ncand);
+  if (sps::launch_stream_fold(sa, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  if (sps::launch_stream_advance(sa, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  hipEvent_t e4 = mark(p, stream);
+  span(p, 2, e0, e1);
+  span(p, 0, e1, e2);
+  span(p, 1, e2, e3);
+  span(p, 2, e3, e4);
+  if (p->timing) ++p->nsearch;
+  if (gulp_offset) *gulp_offset = s->pushed;
+  s->pushed += p->nsamp;
+  s->cur ^= 1;
+  return ok();
+}
+
+int sps_stream_flush(sps_stream* s, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand, int64_t* end_offset) {
+  if (!s || !d_ncand || (!d_cands && s->plan->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+  if (sps::launch_zero_u32(d_ncand, 1, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  const sps::StreamArgs sa = stream_args(s, nullptr, d_cands, d_ncand);
+  if (sps::launch_stream_close(sa, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  if (end_offset) *end_offset = s->pushed;
+  return ok();
+}
+
+int sps_stream_state_size(const sps_stream* s, uint64_t* bytes) {
+  if (!s || !bytes) return fail(SPS_ERR_INVALID_ARG);
+  *bytes = stream_state_bytes(s);
+  return ok();
+}
+
+int sps_stream_save(sps_stream* s, hipStream_t stream, void* host_buf, uint64_t bytes) {
+  if (!s || !host_buf || bytes < stream_state_bytes(s)) return fail(SPS_ERR_INVALID_ARG);
+  if (hipStreamSynchronize(stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  const sps_plan* p = s->plan;
+  StreamHeader h;
+  std::memset(&h, 0, sizeof(h));
+  h.magic = kStreamMagic;
+  h.pushed = s->pushed;
+  h.ndm = p->ndm; h.nsamp = p->nsamp; h.Hx = s->Hx; h.nw = p->nw;
+  h.max_width = p->max_width; h.baseline_len = p->baseline_len;
+  if (hipMemcpy(&h.tmin, s->tmin, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) return fail(SPS_ERR_HIP);
+  char* o = static_cast<char*>(host_buf);
+  std::memcpy(o, &h, sizeof(h));
+  o += sizeof(h);
+  const size_t hb = (size_t)p->ndm * s->Hx * sizeof(float);
+  if (hipMemcpy(o, s->hist[s->cur], hb, hipMemcpyDeviceToHost) != hipSuccess) return fail(SPS_ERR_HIP);
+  o += hb;
+  const size_t mb = (size_t)s->Hb * sizeof(int32_t);
+  if (hipMemcpy2D(o, mb, s->med[s->cur], (size_t)s->nbv * sizeof(int32_t), mb, p->ndm, hipMemcpyDeviceToHost) !=
+      hipSuccess) return fail(SPS_ERR_HIP);
+  o += mb * p->ndm;
+  if (hipMemcpy2D(o, mb, s->mad[s->cur], (size_t)s->nbv * sizeof(int32_t), mb, p->ndm, hipMemcpyDeviceToHost) !=
+      hipSuccess) return fail(SPS_ERR_HIP);
+  o += mb * p->ndm;
+  if (hipMemcpy(o, s->carry, (size_t)p->ndm * p->nw * sizeof(sps::RunSum), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(SPS_ERR_HIP);
+  return ok();
+}
+
+int sps_stream_restore(sps_stream* s, hipStream_t stream, const void* host_buf, uint64_t bytes) {
+  if (!s || !host_buf || bytes < stream_state_bytes(s)) return fail(SPS_ERR_INVALID_ARG);
+  const sps_plan* p = s->plan;
+  StreamHeader h;
+  std::memcpy(&h, host_buf, sizeof(h));
+  if (h.magic != kStreamMagic || h.ndm != p->ndm || h.nsamp != p->nsamp || h.Hx != s->Hx || h.nw != p->nw ||
+      h.max_width != p->max_width || h.baseline_len != p->baseline_len || h.tmin < 0 || h.tmin > s->Hx)
+    return fail(SPS_ERR_INVALID_ARG);
+  if (hipStreamSynchronize(stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  const char* o = static_cast<const char*>(host_buf) + sizeof(h);
+  const size_t hb = (size_t)p->ndm * s->Hx * sizeof(float);
+  if (hipMemcpy(s->hist[s->cur], o, hb, hipMemcpyHostToDevice) != hipSuccess) return fail(SPS_ERR_HIP);
+  o += hb;
+  const size_t mb = (size_t)s->Hb * sizeof(int32_t);
+  if (hipMemcpy2D(s->med[s->cur], (size_t)s->nbv * sizeof(int32_t), o, mb, mb, p->ndm, hipMemcpyHostToDevice) !=
+      hipSuccess) return fail(SPS_ERR_HIP);
+  o += mb * p->ndm;
+  if (hipMemcpy2D(s->mad[s->cur], (size_t)s->nbv * sizeof(int32_t), o, mb, mb, p->ndm, hipMemcpyHostToDevice) !=
+      hipSuccess) return fail(SPS_ERR_HIP);
+  o += mb * p->ndm;
+  if (hipMemcpy(s->carry, o, (size_t)p->ndm * p->nw * sizeof(sps::RunSum), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(SPS_ERR_HIP);
+  if (hipMemcpy(s->tmin, &h.tmin, sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) return fail(SPS_ERR_HIP);
+  s->pushed = h.pushed;
+  return ok();
 }
 
 }  // extern "C"

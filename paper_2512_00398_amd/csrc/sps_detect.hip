@@ -50,12 +50,13 @@ struct Emitter {
   uint32_t dm;
   uint32_t width;
   bool writer;          // the one thread that writes (lane 0 in wave code)
+  int32_t soff;         // emitted sample = position - soff
 };
 
 __device__ __forceinline__ void emit(const Emitter& E, int32_t sample, int32_t S, double den) {
   if (!E.writer) return;
   sps_cand c;
-  c.sample = sample;
+  c.sample = sample - E.soff;
   c.dm_idx = E.dm;
   c.width = E.width;
   c.snr = (float)((double)S / den);
@@ -184,7 +185,7 @@ __device__ __forceinline__ int group_shift(int w) {
 //   C  copy those candidates out; run pass over step c's flagged widths
 //   D  (no barrier) owner waves fold step c into their widths' summaries
 // Samples, medians and MADs are fetched one step ahead of their use.
-template <int NW>
+template <int NW, bool VIRT>
 __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
   const int nw = NW > 0 ? NW : A.nw;
   __shared__ uint32_t ring[kRing];
@@ -203,17 +204,23 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
   const int row = blockIdx.x / A.nseg;
   const int seg = blockIdx.x - row * A.nseg;
   const int N = A.N;
-  const int s0 = seg * A.seg_len;
+  const int s0 = A.seg_base + seg * A.seg_len;
   const int s1 = min(N, s0 + A.seg_len);
-  const float* xr = A.x + (int64_t)row * A.ld;
+  // virtual sample t: t < Hx from the history row, else x row at t - Hx
+  const float* xr = A.x + (int64_t)row * A.ld - (VIRT ? A.Hx : 0);
+  const float* hr = VIRT ? A.hist + (int64_t)row * A.ldh : nullptr;
   const int32_t* medr = A.med + (int64_t)row * A.nblocks;
   const int32_t* madr = A.mad + (int64_t)row * A.nblocks;
   const int emax = min(s1 - s0 + A.maxw - 1, N - s0);  // last window end needed
   const int nsteps = (emax + 64) / kC + 1;              // + group shift headroom
-  const bool vec = ((reinterpret_cast<uintptr_t>(xr) & 15u) == 0);
+  const bool vec = ((reinterpret_cast<uintptr_t>(A.x + (int64_t)row * A.ld) & 15u) == 0) &&
+                   (!VIRT || ((reinterpret_cast<uintptr_t>(hr) & 15u) == 0));
+  const int tmin = A.tmin ? *A.tmin : 0;
   const uint32_t dm = (uint32_t)row + A.row_offset;
   const int e_row = N - s0;  // E <= N - s0      <=> i <= N - w
   const int e_seg = s1 - s0; // E < s1 - s0 + w  <=> i < s1
+  // E >= e_lo0 and E >= tmin - s0 + w: window ends after e_first, starts at or after tmin
+  const int e_lo0 = A.e_first - s0, e_lo1 = tmin - s0;
 
   // bound-table thread: (width tj, group tg)
   const bool tthr = tid < nw * kGroups;
@@ -232,14 +239,16 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
     mk = 0; f0 = f1 = f2 = f3 = 0.f;
     if (t0 < N) {
       mk = medr[t0 >> 6];
+      // a step never straddles the history end (both are multiples of 1024)
+      const float* src = (VIRT && s0 + c * kC < A.Hx) ? hr : xr;
       if (vec && t0 + 3 < N) {
-        const float4 v = *reinterpret_cast<const float4*>(xr + t0);
+        const float4 v = *reinterpret_cast<const float4*>(src + t0);
         f0 = v.x; f1 = v.y; f2 = v.z; f3 = v.w;
       } else {
-        f0 = xr[t0];
-        if (t0 + 1 < N) f1 = xr[t0 + 1];
-        if (t0 + 2 < N) f2 = xr[t0 + 2];
-        if (t0 + 3 < N) f3 = xr[t0 + 3];
+        f0 = src[t0];
+        if (t0 + 1 < N) f1 = src[t0 + 1];
+        if (t0 + 2 < N) f2 = src[t0 + 2];
+        if (t0 + 3 < N) f3 = src[t0 + 3];
       }
     }
   };
@@ -247,10 +256,10 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
   uint32_t p0, p1, p2, p3, incl;
   auto prefix = [&](int c, int mk, float f0, float f1, float f2, float f3) {
     const int t0 = s0 + c * kC + 4 * tid;
-    const int r0 = t0 < N ? __float2int_rz(f0) - mk : 0;
-    const int r1 = t0 + 1 < N ? __float2int_rz(f1) - mk : 0;
-    const int r2 = t0 + 2 < N ? __float2int_rz(f2) - mk : 0;
-    const int r3 = t0 + 3 < N ? __float2int_rz(f3) - mk : 0;
+    const int r0 = t0 < N ? (int)f0 - mk : 0;
+    const int r1 = t0 + 1 < N ? (int)f1 - mk : 0;
+    const int r2 = t0 + 2 < N ? (int)f2 - mk : 0;
+    const int r3 = t0 + 3 < N ? (int)f3 - mk : 0;
     p0 = (uint32_t)r0; p1 = p0 + (uint32_t)r1; p2 = p1 + (uint32_t)r2; p3 = p2 + (uint32_t)r3;
     incl = (uint32_t)wave_scan_incl((int)p3);
     if (lane == 63) wtot[c & 1][wave] = incl;
@@ -308,7 +317,8 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
     }
     {
       // interior step: every position of every width is valid, no masks needed
-      const bool clean = cC - 64 >= A.maxw && cC + kC - 1 <= min(e_seg, e_row - A.maxw);
+      const bool clean = cC - 64 >= max(A.maxw, max(e_lo0, e_lo1 + A.maxw)) &&
+                         cC + kC - 1 <= min(e_seg, e_row - A.maxw);
       uint32_t flagged = 0u;
       auto fast = [&](auto CLEAN) {
         int cur_shift = -1;
@@ -338,7 +348,8 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
               acc |= hit;
             } else {
               const int vhi = min(e_seg + w - 1, e_row);
-              acc |= hit & lane_range(w - e0, vhi - e0);
+              const int vlo = max(w, max(e_lo0, e_lo1 + w));
+              acc |= hit & lane_range(vlo - e0, vhi - e0);
             }
           }
           flagged |= acc ? (1u << j) : 0u;
@@ -367,7 +378,9 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
       const int w = 1 << j, sh = group_shift(w);
       const int eg = cC - sh + 256 * wave;
       const int vhi = min(e_seg + w - 1, e_row);
-      const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, lane == 0};
+      const int vlo = max(w, max(e_lo0, e_lo1 + w));
+      const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, lane == 0,
+                       A.sample_offset};
       RunSum acc = rs_empty();
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -377,7 +390,7 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
         const int lo = readfirst(tlo[j][g]), hi = readfirst(thi[j][g]);
         const double d = tden[j][g];
         const bool above = S > lo && ((S >= hi && hi != INT_MAX) || (double)S / d > A.theta);
-        const uint64_t V = lane_range(w - e0, vhi - e0);
+        const uint64_t V = lane_range(vlo - e0, vhi - e0);
         const uint64_t M = ballot(above) & V;
         const RunSum gs = group_summary(M, V, S, d, s0 + e0 - w, lane, em);
         acc = rs_combine(acc, gs, em);
@@ -390,7 +403,8 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
     // ---- D: width j is owned by wave j % 4
     for (int j = wave; j < nw; j += 4) {
       const int w = 1 << j, sh = group_shift(w);
-      const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, lane == 0};
+      const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, lane == 0,
+                       A.sample_offset};
       RunSum cj = carry[j];
       bool dirty = false;
       if ((smask >> j) & 1u) {
@@ -398,7 +412,8 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
         dirty = true;
       } else {
         // nothing above for width j: a non-empty step closes an open run
-        const int elo = max(cC - sh, w), ehi = min(cC - sh + kC - 1, min(e_seg + w - 1, e_row));
+        const int elo = max(cC - sh, max(w, max(e_lo0, e_lo1 + w)));
+        const int ehi = min(cC - sh + kC - 1, min(e_seg + w - 1, e_row));
         if (elo <= ehi) {
           if (!(cj.flags & kNonEmpty)) {
             cj.flags = kNonEmpty;
@@ -419,8 +434,9 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
   const int lb = (nsteps - 1) & 1;  // staging buffer of the last step
   for (int j = wave; j < nw; j += 4) {
     const RunSum cj = carry[j];
-    const Emitter em{cbuf[lb], &cbuf_n[lb], A.cands, A.ncand, A.cap, dm, (uint32_t)(1 << j), lane == 0};
-    if (A.nseg == 1) rs_close(cj, em);
+    const Emitter em{cbuf[lb], &cbuf_n[lb], A.cands, A.ncand, A.cap, dm, (uint32_t)(1 << j), lane == 0,
+                     A.sample_offset};
+    if (A.nseg == 1 && !A.keep_edges) rs_close(cj, em);
     else if (lane == 0) A.frag[((int64_t)row * nw + j) * A.nseg + seg] = cj;
   }
   __syncthreads();
@@ -440,11 +456,72 @@ __global__ __launch_bounds__(256) void k_fixup(DetectArgs A) {
   if (t >= A.rows * A.nw) return;
   const int row = t / A.nw, j = t - row * A.nw;
   const Emitter em{nullptr, nullptr, A.cands, A.ncand, A.cap, (uint32_t)row + A.row_offset, (uint32_t)(1 << j),
-                   true};
+                   true, A.sample_offset};
   const RunSum* f = A.frag + (int64_t)t * A.nseg;
   RunSum acc = rs_empty();
   for (int s = 0; s < A.nseg; ++s) acc = rs_combine(acc, f[s], em);
   rs_close(acc, em);
+}
+
+__device__ __forceinline__ RunSum rs_shift(RunSum r, int d) {
+  r.hi += d;
+  r.ti += d;
+  return r;
+}
+
+// Streaming, one (row, width) per thread: append this push's segment
+// summaries to the carried one. A run that touches the stream's first
+// position and has ended is reported here; everything still open is carried
+// with positions re-based on the next gulp.
+__global__ __launch_bounds__(256) void k_stream_fold(StreamArgs A) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= A.rows * A.nw) return;
+  const int row = t / A.nw, j = t - row * A.nw;
+  const Emitter em{nullptr, nullptr, A.cands, A.ncand, A.cap, (uint32_t)row + A.row_offset, (uint32_t)(1 << j),
+                   true, 0};
+  RunSum acc = A.carry[t];
+  const RunSum* f = A.frag + (int64_t)t * A.nseg;
+  for (int s = 0; s < A.nseg; ++s) acc = rs_combine(acc, rs_shift(f[s], -A.Hx), em);
+  if ((acc.flags & kHead) && !(acc.flags & kFull)) {
+    emit(em, acc.hi, acc.hS, acc.hd);
+    acc.flags &= ~kHead;
+  }
+  A.carry[t] = rs_shift(acc, -A.ngulp);
+}
+
+// Streaming flush: the stream has ended, so every carried run is closed.
+__global__ __launch_bounds__(256) void k_stream_close(StreamArgs A) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= A.rows * A.nw) return;
+  const int row = t / A.nw, j = t - row * A.nw;
+  const Emitter em{nullptr, nullptr, A.cands, A.ncand, A.cap, (uint32_t)row + A.row_offset, (uint32_t)(1 << j),
+                   true, 0};
+  rs_close(A.carry[t], em);
+  A.carry[t] = rs_empty();
+}
+
+// Streaming: the next push's history is the last Hx samples (and Hb block
+// statistics) of this push's virtual row; the stream start moves down by
+// the gulp length. Grid: (chunks, rows).
+__global__ __launch_bounds__(256) void k_stream_advance(StreamArgs A) {
+  const int row = blockIdx.y;
+  const int nbg = A.nbv - A.Hb;
+  const float* hin = A.hist_in + (int64_t)row * A.Hx;
+  const float* gin = A.gulp + (int64_t)row * A.ngulp;
+  float* hout = A.hist_out + (int64_t)row * A.Hx;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < A.Hx; t += gridDim.x * blockDim.x) {
+    const int v = t + A.ngulp;
+    hout[t] = v < A.Hx ? hin[v] : gin[v - A.Hx];
+  }
+  const int32_t* mi = A.med_in + (int64_t)row * A.nbv;
+  const int32_t* di = A.mad_in + (int64_t)row * A.nbv;
+  int32_t* mo = A.med_out + (int64_t)row * A.nbv;
+  int32_t* dout = A.mad_out + (int64_t)row * A.nbv;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < A.Hb; k += gridDim.x * blockDim.x) {
+    mo[k] = mi[k + nbg];
+    dout[k] = di[k + nbg];
+  }
+  if (row == 0 && blockIdx.x == 0 && threadIdx.x == 0) *A.tmin = max(0, *A.tmin - A.ngulp);
 }
 
 __global__ void k_zero_u32(uint32_t* p, int n) {
@@ -457,12 +534,15 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 hipError_t launch_detect(const DetectArgs& a, hipStream_t s) {
   const int64_t grid = (int64_t)a.rows * a.nseg;
   if (grid <= 0) return hipSuccess;
-  if (a.nw == 13)
-    hipLaunchKernelGGL(k_detect<13>, dim3((unsigned)grid), dim3(256), 0, s, a);
-  else if (a.nw == 7)
-    hipLaunchKernelGGL(k_detect<7>, dim3((unsigned)grid), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_detect<0>, dim3((unsigned)grid), dim3(256), 0, s, a);
+  const dim3 g((unsigned)grid), b(256);
+  if (a.Hx > 0) {
+    if (a.nw == 13) hipLaunchKernelGGL((k_detect<13, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_detect<0, true>), g, b, 0, s, a);
+  } else {
+    if (a.nw == 13) hipLaunchKernelGGL((k_detect<13, false>), g, b, 0, s, a);
+    else if (a.nw == 7) hipLaunchKernelGGL((k_detect<7, false>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_detect<0, false>), g, b, 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -470,6 +550,27 @@ hipError_t launch_fixup(const DetectArgs& a, hipStream_t s) {
   const int n = a.rows * a.nw;
   if (n <= 0 || a.nseg <= 1) return hipSuccess;
   hipLaunchKernelGGL(k_fixup, dim3((n + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_fold(const StreamArgs& a, hipStream_t s) {
+  const int n = a.rows * a.nw;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stream_fold, dim3((n + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_close(const StreamArgs& a, hipStream_t s) {
+  const int n = a.rows * a.nw;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stream_close, dim3((n + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_advance(const StreamArgs& a, hipStream_t s) {
+  if (a.rows <= 0) return hipSuccess;
+  const int chunks = (a.Hx + 4095) / 4096;
+  hipLaunchKernelGGL(k_stream_advance, dim3(chunks > 0 ? chunks : 1, a.rows), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

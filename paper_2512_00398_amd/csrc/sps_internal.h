@@ -36,14 +36,23 @@ static_assert(sizeof(RunSum) == 40, "RunSum layout");
 enum : int32_t { kNonEmpty = 1, kFull = 2, kHead = 4, kTail = 8 };
 
 // Launch descriptors (passed by value as kernel arguments).
+//
+// The kernels see each row as "virtual" samples [0, N): the first Hx come
+// from `hist` (the device-resident history of a stream; Hx = 0 outside
+// streaming) and the rest from `x`. Hx is a multiple of 1024.
 struct StatsArgs {
   const float* x;
-  int64_t ld;          // row stride in samples
-  int32_t N, L;
-  int32_t nblocks;     // ceil(N / 64)
+  int64_t ld;          // row stride of x in samples
+  const float* hist;
+  int64_t ldh;
+  int32_t Hx;
+  int32_t N, L;        // virtual row length, baseline window
+  int32_t nblocks;     // ceil(N / 64): row stride of med / mad
+  int32_t kb_first;    // first block computed (blocks below it are carried in)
   int32_t seg_blocks;  // blocks per chain segment
   int32_t nseg;        // segments per row
   int32_t nchains;     // rows * nseg
+  const int32_t* tmin; // device: no window reaches below *tmin (null: 0)
   int32_t* med;        // [rows][nblocks]
   int32_t* mad;
 };
@@ -51,7 +60,10 @@ struct StatsArgs {
 struct DetectArgs {
   const float* x;
   int64_t ld;
-  int32_t N;
+  const float* hist;
+  int64_t ldh;
+  int32_t Hx;
+  int32_t N;           // virtual row length
   int32_t nblocks;
   int32_t nw;          // number of widths (w = 1 << j)
   int32_t maxw;
@@ -59,14 +71,43 @@ struct DetectArgs {
   const int32_t* mad;
   double theta;        // (double)(float) threshold
   double sqrtw[kMaxWidths];
-  int32_t seg_len;     // positions per segment (multiple of the step size)
+  int32_t seg_base;    // first position of segment 0 (multiple of 1024)
+  int32_t seg_len;     // positions per segment (multiple of 1024)
   int32_t nseg;        // segments per row
   int32_t rows;
+  int32_t e_first;     // evaluate only windows ending at or after e_first
+  const int32_t* tmin; // device: evaluate only positions >= *tmin (null: 0)
+  int32_t sample_offset;  // emitted sample = position - sample_offset
+  int32_t keep_edges;  // 1: always leave row-edge runs to a fix-up kernel
   uint32_t row_offset; // added to dm_idx of emitted candidates
   sps_cand* cands;
   uint32_t* ncand;
   uint32_t cap;
-  RunSum* frag;        // [rows][nw][nseg] summaries of multi-segment rows
+  RunSum* frag;        // [rows][nw][nseg] summaries of segment edges
+};
+
+// Streaming: fold one push's segment summaries into the carried per-(row,
+// width) summaries, and roll the history forward.
+struct StreamArgs {
+  int32_t rows, nw, nseg;
+  int32_t Hx;          // history samples (multiple of 1024)
+  int32_t Hb;          // history blocks = Hx / 64
+  int32_t ngulp;       // samples of the gulp just pushed
+  int32_t nbv;         // virtual blocks per row = Hb + ceil(ngulp / 64)
+  const RunSum* frag;  // [rows][nw][nseg], positions in virtual coordinates
+  RunSum* carry;       // [rows][nw], positions relative to the current gulp
+  const float* gulp;   // [rows][ngulp]
+  const float* hist_in;  // [rows][Hx]
+  float* hist_out;
+  const int32_t* med_in;  // [rows][nbv] of this push
+  const int32_t* mad_in;
+  int32_t* med_out;       // [rows][nbv] of the next push (history part written)
+  int32_t* mad_out;
+  int32_t* tmin;          // device scalar
+  uint32_t row_offset;
+  sps_cand* cands;
+  uint32_t* ncand;
+  uint32_t cap;
 };
 
 // Host-side launchers (defined in the .hip files).
@@ -74,5 +115,8 @@ hipError_t launch_block_stats(const StatsArgs& a, int hist_bins, hipStream_t s);
 hipError_t launch_detect(const DetectArgs& a, hipStream_t s);
 hipError_t launch_fixup(const DetectArgs& a, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
+hipError_t launch_stream_fold(const StreamArgs& a, hipStream_t s);
+hipError_t launch_stream_advance(const StreamArgs& a, hipStream_t s);
+hipError_t launch_stream_close(const StreamArgs& a, hipStream_t s);
 
 }  // namespace sps

@@ -27,7 +27,19 @@ namespace sps {
 
 namespace {
 
-__device__ __forceinline__ int ld_int(const float* row, int t) { return __float2int_rz(row[t]); }
+// Virtual row: samples t < Hx come from the stream history h, the rest from
+// the input g (g[t - Hx]). VIRT = false: no history, t indexes g directly.
+template <bool VIRT>
+struct RowRef {
+  const float* g;
+  const float* h;
+  int Hx;
+  __device__ __forceinline__ float at(int t) const {
+    if (VIRT) return t < Hx ? h[t] : g[t - Hx];
+    return g[t];
+  }
+  __device__ __forceinline__ int iat(int t) const { return (int)at(t); }
+};
 
 __device__ __forceinline__ uint32_t absdiff(int v, int m) {
   return v >= m ? (uint32_t)v - (uint32_t)m : (uint32_t)m - (uint32_t)v;
@@ -42,10 +54,10 @@ __device__ __forceinline__ int hist_get(const uint32_t* H, int idx) {
   return (int)((H[idx >> 1] >> ((idx & 1) << 4)) & 0xFFFFu);
 }
 
-template <int NB>
+template <int NB, bool VIRT>
 struct Chain {
   uint32_t* H;        // this wave's NB/2 histogram words
-  const float* row;
+  RowRef<VIRT> row;
   int L;
   int lane;
   int base;           // value of histogram bin 0
@@ -59,8 +71,8 @@ struct Chain {
 // MODE 0 keys are x ^ 0x80000000 (order of int32 x), MODE 1 keys are |x - m|.
 // Four passes over the window, 8 key bits each; H[0..255] serves as the
 // digit histogram (callers rebuild or abandon the value histogram afterwards).
-template <int MODE>
-__device__ uint32_t radix_select(uint32_t* H, const float* row, int lo, int hi, int rank, int m, int lane) {
+template <int MODE, bool VIRT>
+__device__ uint32_t radix_select(uint32_t* H, const RowRef<VIRT>& row, int lo, int hi, int rank, int m, int lane) {
   uint32_t prefix = 0, pmask = 0;
   for (int shift = 24; shift >= 0; shift -= 8) {
     for (int i = lane; i < 256; i += 64) H[i] = 0;
@@ -68,7 +80,7 @@ __device__ uint32_t radix_select(uint32_t* H, const float* row, int lo, int hi, 
     for (int t0 = lo; t0 < hi; t0 += 64) {
       const int t = t0 + lane;
       if (t < hi) {
-        const int v = ld_int(row, t);
+        const int v = row.iat(t);
         const uint32_t key = MODE == 0 ? ((uint32_t)v ^ 0x80000000u) : absdiff(v, m);
         if ((key & pmask) == prefix) atomicAdd(&H[(key >> shift) & 255u], 1u);
       }
@@ -99,8 +111,8 @@ __device__ uint32_t radix_select(uint32_t* H, const float* row, int lo, int hi, 
 
 // Recount the window [lo, hi) into a histogram whose bin 0 is `base`;
 // returns #{x < base}.
-template <int NB>
-__device__ int rebuild(Chain<NB>& c, int lo, int hi, int base) {
+template <int NB, bool VIRT>
+__device__ int rebuild(Chain<NB, VIRT>& c, int lo, int hi, int base) {
   c.base = base;
   for (int i = c.lane; i < NB / 2; i += 64) c.H[i] = 0;
   wave_lds_fence();
@@ -108,7 +120,7 @@ __device__ int rebuild(Chain<NB>& c, int lo, int hi, int base) {
   for (int t0 = lo; t0 < hi; t0 += 64) {
     const int t = t0 + c.lane;
     const bool ok = t < hi;
-    const int v = ok ? ld_int(c.row, t) : 0;
+    const int v = ok ? c.row.iat(t) : 0;
     const uint32_t idx = (uint32_t)v - (uint32_t)base;
     if (ok && idx < (uint32_t)NB) hist_add(c.H, idx, 1u);
     below += popc(ballot(ok && v < base));
@@ -120,8 +132,8 @@ __device__ int rebuild(Chain<NB>& c, int lo, int hi, int base) {
 
 // Median and MAD from the whole histogram, given #{x < base}. Fails (returns
 // false) when a needed quantile lies outside the histogram's range.
-template <int NB>
-__device__ bool full_query(Chain<NB>& c, int below) {
+template <int NB, bool VIRT>
+__device__ bool full_query(Chain<NB, VIRT>& c, int below) {
   const int rho = (c.n - 1) >> 1;
   if (below > rho) return false;
   int acc = below, m2 = 0, cm2 = 0;
@@ -169,8 +181,8 @@ __device__ bool full_query(Chain<NB>& c, int below) {
 
 // Local query: new median within 31 values of the old one and new MAD within
 // 31 of the old one (the usual case). Returns false when it cannot decide.
-template <int NB>
-__device__ __forceinline__ bool fast_query(Chain<NB>& c) {
+template <int NB, bool VIRT>
+__device__ __forceinline__ bool fast_query(Chain<NB, VIRT>& c) {
   const int rho = (c.n - 1) >> 1;
   const int im = c.m - c.base, iL = c.m - c.d - c.base, iU = c.m + c.d + 1 - c.base;
   if (im - 32 < 0 || im + 32 > NB || iL - 32 < 0 || iU + 32 > NB) return false;
@@ -208,11 +220,11 @@ __device__ __forceinline__ bool fast_query(Chain<NB>& c) {
 
 // Exact answer for window [lo, hi) from the samples themselves, then a
 // histogram centred on the median when the data allow one.
-template <int NB>
-__device__ void exact_block(Chain<NB>& c, int lo, int hi) {
+template <int NB, bool VIRT>
+__device__ void exact_block(Chain<NB, VIRT>& c, int lo, int hi) {
   const int rho = (c.n - 1) >> 1;
-  const int m = (int)(radix_select<0>(c.H, c.row, lo, hi, rho, 0, c.lane) ^ 0x80000000u);
-  const uint32_t d = radix_select<1>(c.H, c.row, lo, hi, rho, m, c.lane);
+  const int m = (int)(radix_select<0, VIRT>(c.H, c.row, lo, hi, rho, 0, c.lane) ^ 0x80000000u);
+  const uint32_t d = radix_select<1, VIRT>(c.H, c.row, lo, hi, rho, m, c.lane);
   c.m = m;
   c.d = (int)d;
   if (d < (uint32_t)(NB / 2 - 128)) {
@@ -224,11 +236,11 @@ __device__ void exact_block(Chain<NB>& c, int lo, int hi) {
   }
 }
 
-template <int NB>
-__device__ void chain_init(Chain<NB>& c, int lo, int hi) {
+template <int NB, bool VIRT>
+__device__ void chain_init(Chain<NB, VIRT>& c, int lo, int hi) {
   // Centre the first histogram on the median of the last <= 256 window samples.
   const int slo = max(lo, hi - 256);
-  const int g = (int)(radix_select<0>(c.H, c.row, slo, hi, (hi - slo - 1) >> 1, 0, c.lane) ^ 0x80000000u);
+  const int g = (int)(radix_select<0, VIRT>(c.H, c.row, slo, hi, (hi - slo - 1) >> 1, 0, c.lane) ^ 0x80000000u);
   const int below = rebuild(c, lo, hi, g - NB / 2);
   if (!full_query(c, below)) exact_block(c, lo, hi);
 }
@@ -236,8 +248,8 @@ __device__ void chain_init(Chain<NB>& c, int lo, int hi) {
 // Rare path: answer from the whole histogram, recentre it when the quantiles
 // near its edges, or fall back to the exact select. Kept out of line so the
 // unrolled block loop stays small.
-template <int NB>
-__device__ void slow_block(Chain<NB>& c, int lo, int hi) {
+template <int NB, bool VIRT>
+__device__ void slow_block(Chain<NB, VIRT>& c, int lo, int hi) {
   // #{x < base} from the exact count below the old median
   const int im = c.m - c.base;
   int s = 0;
@@ -259,8 +271,8 @@ __device__ void slow_block(Chain<NB>& c, int lo, int hi) {
   exact_block(c, lo, hi);
 }
 
-template <int NB>
-__device__ __forceinline__ void chain_step(Chain<NB>& c, int lo, int hi, bool a_ok, int av, bool b_ok, int bv) {
+template <int NB, bool VIRT>
+__device__ __forceinline__ void chain_step(Chain<NB, VIRT>& c, int lo, int hi, bool a_ok, int av, bool b_ok, int bv) {
   c.n += popc(ballot(a_ok)) - popc(ballot(b_ok));
   if (c.raw) {
     exact_block(c, lo, hi);
@@ -277,8 +289,10 @@ __device__ __forceinline__ void chain_step(Chain<NB>& c, int lo, int hi, bool a_
   if (!fast_query(c)) slow_block(c, lo, hi);
 }
 
-// WPG chains (waves) per workgroup; LDS = WPG * NB * 2 bytes.
-template <int NB, int WPG>
+// WPG chains (waves) per workgroup; LDS = WPG * NB * 2 bytes. Blocks
+// [kb_first, nblocks) of every row are computed; windows never reach below
+// the device value *tmin (the first sample of a stream).
+template <int NB, int WPG, bool VIRT>
 __global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
   __shared__ uint32_t hist[WPG][NB / 2];
   // wave index kept in a VGPR: the chain state then stays on the vector unit,
@@ -289,19 +303,22 @@ __global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
   if (chain >= a.nchains) return;  // whole wave leaves; no block barriers are used
   const int row = chain / a.nseg;
   const int seg = chain - row * a.nseg;
-  const int kb0 = seg * a.seg_blocks;
+  const int kb0 = a.kb_first + seg * a.seg_blocks;
   const int kb1 = min(a.nblocks, kb0 + a.seg_blocks);
   const int N = a.N, L = a.L;
-  Chain<NB> c;
+  const int t0 = a.tmin ? *a.tmin : 0;
+  Chain<NB, VIRT> c;
   c.H = hist[wave];
-  c.row = a.x + (int64_t)row * a.ld;
+  c.row.g = a.x + (int64_t)row * a.ld;
+  c.row.h = VIRT ? a.hist + (int64_t)row * a.ldh : nullptr;
+  c.row.Hx = VIRT ? a.Hx : 0;
   c.L = L;
   c.lane = lane;
   int32_t* med = a.med + (int64_t)row * a.nblocks;
   int32_t* mad = a.mad + (int64_t)row * a.nblocks;
 
   {
-    const int e = min(kb0 * kStride + kStride, N), lo = max(0, e - L);
+    const int e = min(kb0 * kStride + kStride, N), lo = max(t0, e - L);
     c.n = e - lo;
     chain_init(c, lo, e);
     if (lane == 0) { med[kb0] = c.m; mad[kb0] = c.d; }
@@ -310,9 +327,9 @@ __global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
   // Samples entering / leaving the window at block kk, prefetched 4 blocks ahead.
   auto fetch = [&](int kk, float& va, float& vb) {
     const int ep = min(kk * kStride, N), e = min(kk * kStride + kStride, N);
-    const int lp = max(0, ep - L), l2 = max(0, e - L);
-    va = (lane < e - ep) ? c.row[ep + lane] : 0.f;
-    vb = (lane < l2 - lp) ? c.row[lp + lane] : 0.f;
+    const int lp = max(t0, ep - L), l2 = max(t0, e - L);
+    va = (lane < e - ep) ? c.row.at(ep + lane) : 0.f;
+    vb = (lane < l2 - lp) ? c.row.at(lp + lane) : 0.f;
   };
   float pa[4], pb[4];
 #pragma unroll
@@ -326,8 +343,8 @@ __global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
       fetch(kk + 4, pa[j], pb[j]);
       if (kk < kb1) {
         const int ep = min(kk * kStride, N), e = min(kk * kStride + kStride, N);
-        const int lp = max(0, ep - L), l2 = max(0, e - L);
-        chain_step(c, l2, e, lane < e - ep, __float2int_rz(va), lane < l2 - lp, __float2int_rz(vb));
+        const int lp = max(t0, ep - L), l2 = max(t0, e - L);
+        chain_step(c, l2, e, lane < e - ep, (int)va, lane < l2 - lp, (int)vb);
         if (lane == 0) { med[kk] = c.m; mad[kk] = c.d; }
       }
     }
@@ -338,10 +355,14 @@ __global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
 
 hipError_t launch_block_stats(const StatsArgs& a, int hist_bins, hipStream_t s) {
   if (a.nchains <= 0) return hipSuccess;
-  if (hist_bins == 16384)
-    hipLaunchKernelGGL((k_block_stats<16384, 2>), dim3((a.nchains + 1) / 2), dim3(128), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_block_stats<4096, 4>), dim3((a.nchains + 3) / 4), dim3(256), 0, s, a);
+  const bool virt = a.Hx > 0;
+  if (hist_bins == 16384) {
+    if (virt) hipLaunchKernelGGL((k_block_stats<16384, 2, true>), dim3((a.nchains + 1) / 2), dim3(128), 0, s, a);
+    else hipLaunchKernelGGL((k_block_stats<16384, 2, false>), dim3((a.nchains + 1) / 2), dim3(128), 0, s, a);
+  } else {
+    if (virt) hipLaunchKernelGGL((k_block_stats<4096, 4, true>), dim3((a.nchains + 3) / 4), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_block_stats<4096, 4, false>), dim3((a.nchains + 3) / 4), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 

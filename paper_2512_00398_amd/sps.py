@@ -46,6 +46,13 @@ EXPORTS = [
     ("sps_plan_set", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64]),
     ("sps_plan_get", ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
     ("sps_timing_read", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    ("sps_stream_create", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_void_p)]),
+    ("sps_stream_push", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
+    ("sps_stream_flush", ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
+    ("sps_stream_state_size", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64)]),
+    ("sps_stream_save", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64]),
+    ("sps_stream_restore", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64]),
+    ("sps_stream_destroy", None, [_P]),
     ("sps_last_error", ctypes.c_int, []),
     ("sps_error_string", ctypes.c_char_p, [ctypes.c_int]),
 ]
@@ -176,6 +183,71 @@ class Plan:
     def close(self) -> None:
         if getattr(self, "_h", None):
             load().sps_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Stream:
+    """Gulp-by-gulp search of one observation (see include/sps.h)."""
+
+    def __init__(self, plan: Plan):
+        self.plan = plan
+        h = ctypes.c_void_p()
+        rc = load().sps_stream_create(plan._h, ctypes.byref(h))
+        if rc:
+            raise SpsError(rc, "sps_stream_create")
+        self._h = h.value
+
+    def push(self, gulp, cands, ncand, stream=None) -> int:
+        """Enqueue one gulp; returns the global index of its first sample."""
+        _check_series(gulp, self.plan.ndm, self.plan.nsamp)
+        off = ctypes.c_int64()
+        rc = load().sps_stream_push(self._h, gulp.data_ptr(), _stream_handle(stream), cands.data_ptr(),
+                                    ncand.data_ptr(), ctypes.byref(off))
+        if rc:
+            raise SpsError(rc, "sps_stream_push")
+        return int(off.value)
+
+    def flush(self, cands, ncand, stream=None) -> int:
+        """Emit the runs still open; returns the number of samples pushed."""
+        off = ctypes.c_int64()
+        rc = load().sps_stream_flush(self._h, _stream_handle(stream), cands.data_ptr(), ncand.data_ptr(),
+                                     ctypes.byref(off))
+        if rc:
+            raise SpsError(rc, "sps_stream_flush")
+        return int(off.value)
+
+    def save(self, stream=None) -> bytes:
+        n = ctypes.c_uint64()
+        rc = load().sps_stream_state_size(self._h, ctypes.byref(n))
+        if rc:
+            raise SpsError(rc, "sps_stream_state_size")
+        buf = ctypes.create_string_buffer(int(n.value))
+        rc = load().sps_stream_save(self._h, _stream_handle(stream), buf, n.value)
+        if rc:
+            raise SpsError(rc, "sps_stream_save")
+        return buf.raw
+
+    def restore(self, state: bytes, stream=None) -> None:
+        buf = ctypes.create_string_buffer(state, len(state))
+        rc = load().sps_stream_restore(self._h, _stream_handle(stream), buf, len(state))
+        if rc:
+            raise SpsError(rc, "sps_stream_restore")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().sps_stream_destroy(self._h)
             self._h = None
 
     def __del__(self):

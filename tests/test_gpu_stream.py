@@ -1,0 +1,113 @@
+"""GPU streaming: gulp-by-gulp search equals the one-shot oracle on the concatenation.
+
+Candidates from every push (sample + gulp offset) and from the final flush
+(sample + end offset) must equal the oracle's candidates for the whole
+observation; checkpoint/restore mid-stream must not change anything.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import compare_cands, exact_equal
+
+pytestmark = pytest.mark.gpu
+
+
+def sps():
+    from paper_2512_00398_amd import sps as m
+    return m
+
+
+def run_stream(x, gulp, max_width, L, theta, restore_after=None, detect_seg=0, stats_seg=0):
+    import torch
+    m = sps()
+    ndm, total = x.shape
+    assert total % gulp == 0
+    print("stream case ndm=%d total=%d gulp=%d w=%d L=%d restore=%s" % (ndm, total, gulp, max_width, L,
+                                                                       restore_after), flush=True)
+    parts = []
+    with m.Plan(ndm, gulp, max_width, L, theta) as plan:
+        if detect_seg:
+            plan.set(m.ATTR_DETECT_SEG, detect_seg)
+        if stats_seg:
+            plan.set(m.ATTR_STATS_SEG, stats_seg)
+        cands, ncand = plan.alloc_cands()
+        st = m.Stream(plan)
+        for g in range(total // gulp):
+            xd = torch.from_numpy(np.ascontiguousarray(x[:, g * gulp:(g + 1) * gulp])).cuda()
+            off = st.push(xd, cands, ncand)
+            torch.cuda.synchronize()
+            assert off == g * gulp
+            c = m.cands_to_numpy(cands, ncand, plan.max_cands)
+            parts.append((c, off))
+            if restore_after is not None and g == restore_after:
+                state = st.save()
+                st.close()
+                st = m.Stream(plan)
+                st.restore(state)
+        end = st.flush(cands, ncand)
+        torch.cuda.synchronize()
+        assert end == total
+        parts.append((m.cands_to_numpy(cands, ncand, plan.max_cands), end))
+        st.close()
+    out = []
+    for c, off in parts:
+        a = np.empty(c.size, dtype=oracle.CAND_DTYPE)
+        a["sample"] = c["sample"].astype(np.int64) + off
+        a["dm_idx"], a["width"], a["snr"] = c["dm_idx"], c["width"], c["snr"]
+        out.append(a)
+    return oracle.sort_cands(np.concatenate(out))
+
+
+CASES = [
+    # gulp shorter than the baseline window (history shifts within itself)
+    dict(name="short-gulps", ndm=6, total=16384, gulp=2048, w=64, L=4096, theta=5.0),
+    # gulp shorter than the widest boxcar
+    dict(name="gulp<maxw", ndm=4, total=8192, gulp=1024, w=2048, L=700, theta=4.0),
+    # minimal gulp of one block
+    dict(name="gulp=64", ndm=3, total=4096, gulp=64, w=128, L=200, theta=3.5),
+    # long gulps, every width, pulses across gulp edges
+    dict(name="long-gulps", ndm=8, total=8 * 8192, gulp=8192, w=4096, L=4096, theta=5.0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c["name"] for c in CASES])
+def test_stream_equals_one_shot(case):
+    b = synth.Block(ndm=case["ndm"], nsamp=case["total"], max_width=case["w"], baseline_len=case["L"],
+                    seed=99, n_pulses=12, pulse_width=(1, min(512, case["w"])), pulse_snr=(6.0, 30.0),
+                    straddle_period=case["gulp"])
+    x = synth.generate(b)
+    got = run_stream(x, case["gulp"], case["w"], case["L"], case["theta"])
+    ref = oracle.search(x, case["w"], case["L"], case["theta"])
+    assert compare_cands(got, ref, case["theta"], case["name"]) == 0
+    assert exact_equal(got, ref)
+    assert ref.size > 0
+
+
+def test_stream_checkpoint_restore_and_tilings():
+    b = synth.Block(ndm=5, nsamp=6 * 4096, max_width=1024, baseline_len=3000, seed=7, n_pulses=10,
+                    pulse_width=(1, 512), pulse_snr=(6.0, 25.0), straddle_period=4096)
+    x = synth.generate(b)
+    ref = oracle.search(x, 1024, 3000, 5.0)
+    plain = run_stream(x, 4096, 1024, 3000, 5.0)
+    restored = run_stream(x, 4096, 1024, 3000, 5.0, restore_after=2)
+    tiled = run_stream(x, 4096, 1024, 3000, 5.0, detect_seg=1024, stats_seg=64)
+    assert exact_equal(plain, ref)
+    assert exact_equal(restored, ref)
+    assert exact_equal(tiled, ref)
+
+
+def test_stream_workload_rows_full_length():
+    # The streaming workload's gulp shape (2^18 samples, 13 widths, window
+    # 16384, pulses straddling gulp edges) on a subset of its rows.
+    cfg = synth.config(3)
+    b = cfg["blocks"][0].with_(ndm=32)
+    gulp = cfg["gulp"]
+    x = synth.generate(b)
+    got = run_stream(x, gulp, b.max_width, b.baseline_len, b.snr_thresh)
+    rows = [0, 13, 31]
+    ref = oracle.search(x, b.max_width, b.baseline_len, b.snr_thresh, rows=rows)
+    sel = np.isin(got["dm_idx"], rows)
+    assert compare_cands(got[sel], ref, b.snr_thresh, "c3-rows") == 0
+    assert exact_equal(got[sel], ref)
