@@ -178,6 +178,13 @@ typedef struct sps_stream sps_stream;
 int sps_stream_create(sps_plan* plan, sps_stream** out);
 int sps_stream_push(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand,
                     int64_t* gulp_offset);
+/* sps_stream_push_graph: the same gulp step replayed from a captured HIP
+ * graph (one per history parity, captured on first use for a given
+ * (d_gulp, d_cands, d_ncand) triple and kept until the triple changes):
+ * pass a fixed, double-buffered input location. Same results as
+ * sps_stream_push. */
+int sps_stream_push_graph(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands,
+                          uint32_t* d_ncand, int64_t* gulp_offset);
 int sps_stream_flush(sps_stream* s, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand, int64_t* end_offset);
 int sps_stream_state_size(const sps_stream* s, uint64_t* bytes);
 int sps_stream_save(sps_stream* s, hipStream_t stream, void* host_buf, uint64_t bytes);

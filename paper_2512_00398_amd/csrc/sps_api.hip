@@ -417,6 +417,10 @@ struct sps_stream {
   sps::RunSum* frag;    // [ndm][nw][nseg]
   int32_t* tmin;        // device: virtual index of the stream's first sample (clamped at 0)
   int64_t pushed;       // samples pushed so far
+  // captured gulp steps, one per history parity, for one (gulp, cands, ncand) triple
+  hipStream_t cap_stream;
+  hipGraphExec_t exec[2];
+  const void* exec_key[3];
 };
 
 namespace {
@@ -473,6 +477,9 @@ void stream_free(sps_stream* s) {
   if (s->carry) (void)hipFree(s->carry);
   if (s->frag) (void)hipFree(s->frag);
   if (s->tmin) (void)hipFree(s->tmin);
+  for (int i = 0; i < 2; ++i)
+    if (s->exec[i]) (void)hipGraphExecDestroy(s->exec[i]);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
 }
 
@@ -548,13 +555,23 @@ void sps_stream_destroy(sps_stream* s) {
   stream_free(s);
 }
 
-int sps_stream_push(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand,
-                    int64_t* gulp_offset) {
-  if (!s || !d_gulp || !d_ncand || (!d_cands && s->plan->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+}  // extern "C"
+
+namespace {
+
+// Enqueue one gulp step reading history buffer `c` (no host state changes;
+// capturable: kernels only). `timed`: record tracing events.
+int stream_enqueue(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand,
+                   int c, bool timed) {
   sps_plan* p = s->plan;
-  const int c = s->cur;
+  struct TimingGuard {  // tracing events are not recorded into captured graphs
+    sps_plan* p;
+    int saved;
+    ~TimingGuard() { p->timing = saved; }
+  } guard{p, p->timing};
+  if (!timed) p->timing = 0;
   hipEvent_t e0 = mark(p, stream);
-  if (sps::launch_zero_u32(d_ncand, 1, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  if (sps::launch_zero_u32(d_ncand, 1, stream) != hipSuccess) return SPS_ERR_HIP;
   hipEvent_t e1 = mark(p, stream);
   sps::StatsArgs a;
   a.x = d_gulp;
@@ -572,7 +589,7 @@ int sps_stream_push(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_
   a.tmin = s->tmin;
   a.med = s->med[c];
   a.mad = s->mad[c];
-  if (sps::launch_block_stats(a, p->hist_bins, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  if (sps::launch_block_stats(a, p->hist_bins, stream) != hipSuccess) return SPS_ERR_HIP;
   hipEvent_t e2 = mark(p, stream);
   sps::DetectArgs d;
   d.x = d_gulp;
@@ -601,19 +618,77 @@ int sps_stream_push(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_
   d.ncand = d_ncand;
   d.cap = (uint32_t)p->max_cands;
   d.frag = s->frag;
-  if (sps::launch_detect(d, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  if (sps::launch_detect(d, stream) != hipSuccess) return SPS_ERR_HIP;
   hipEvent_t e3 = mark(p, stream);
-  const sps::StreamArgs sa = stream_args(s, d_gulp, d_cands, d_ncand);
-  if (sps::launch_stream_fold(sa, stream) != hipSuccess) return fail(SPS_ERR_HIP);
-  if (sps::launch_stream_advance(sa, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  sps::StreamArgs sa = stream_args(s, d_gulp, d_cands, d_ncand);
+  sa.hist_in = s->hist[c];
+  sa.hist_out = s->hist[c ^ 1];
+  sa.med_in = s->med[c];
+  sa.mad_in = s->mad[c];
+  sa.med_out = s->med[c ^ 1];
+  sa.mad_out = s->mad[c ^ 1];
+  if (sps::launch_stream_fold(sa, stream) != hipSuccess) return SPS_ERR_HIP;
+  if (sps::launch_stream_advance(sa, stream) != hipSuccess) return SPS_ERR_HIP;
   hipEvent_t e4 = mark(p, stream);
   span(p, 2, e0, e1);
   span(p, 0, e1, e2);
   span(p, 1, e2, e3);
   span(p, 2, e3, e4);
   if (p->timing) ++p->nsearch;
+  return SPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sps_stream_push(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand,
+                    int64_t* gulp_offset) {
+  if (!s || !d_gulp || !d_ncand || (!d_cands && s->plan->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+  const int rc = stream_enqueue(s, d_gulp, stream, d_cands, d_ncand, s->cur, true);
+  if (rc != SPS_OK) return fail(rc);
   if (gulp_offset) *gulp_offset = s->pushed;
-  s->pushed += p->nsamp;
+  s->pushed += s->plan->nsamp;
+  s->cur ^= 1;
+  return ok();
+}
+
+int sps_stream_push_graph(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands,
+                          uint32_t* d_ncand, int64_t* gulp_offset) {
+  if (!s || !d_gulp || !d_ncand || (!d_cands && s->plan->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+  if (s->exec_key[0] != d_gulp || s->exec_key[1] != d_cands || s->exec_key[2] != d_ncand) {
+    for (int i = 0; i < 2; ++i) {
+      if (s->exec[i]) (void)hipGraphExecDestroy(s->exec[i]);
+      s->exec[i] = nullptr;
+    }
+    s->exec_key[0] = s->exec_key[1] = s->exec_key[2] = nullptr;
+    if (!s->cap_stream && hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess)
+      return fail(SPS_ERR_HIP);
+    for (int i = 0; i < 2; ++i) {
+      hipGraph_t g = nullptr;
+      if (hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return fail(SPS_ERR_HIP);
+      const int rc = stream_enqueue(s, d_gulp, s->cap_stream, d_cands, d_ncand, i, false);
+      const hipError_t ec = hipStreamEndCapture(s->cap_stream, &g);
+      if (rc != SPS_OK || ec != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return fail(SPS_ERR_HIP);
+      }
+      const hipError_t ei = hipGraphInstantiate(&s->exec[i], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        s->exec[i] = nullptr;
+        (void)hipGetLastError();
+        return fail(SPS_ERR_HIP);
+      }
+    }
+    s->exec_key[0] = d_gulp;
+    s->exec_key[1] = d_cands;
+    s->exec_key[2] = d_ncand;
+  }
+  if (hipGraphLaunch(s->exec[s->cur], stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  if (gulp_offset) *gulp_offset = s->pushed;
+  s->pushed += s->plan->nsamp;
   s->cur ^= 1;
   return ok();
 }

@@ -48,6 +48,7 @@ EXPORTS = [
     ("sps_timing_read", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     ("sps_stream_create", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_void_p)]),
     ("sps_stream_push", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
+    ("sps_stream_push_graph", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
     ("sps_stream_flush", ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
     ("sps_stream_state_size", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64)]),
     ("sps_stream_save", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64]),
@@ -209,14 +210,18 @@ class Stream:
             raise SpsError(rc, "sps_stream_create")
         self._h = h.value
 
-    def push(self, gulp, cands, ncand, stream=None) -> int:
-        """Enqueue one gulp; returns the global index of its first sample."""
+    def push(self, gulp, cands, ncand, stream=None, graph: bool = False) -> int:
+        """Enqueue one gulp; returns the global index of its first sample.
+
+        graph=True replays a captured HIP graph of the gulp step (pass the
+        same gulp/cands/ncand buffers each time)."""
         _check_series(gulp, self.plan.ndm, self.plan.nsamp)
         off = ctypes.c_int64()
-        rc = load().sps_stream_push(self._h, gulp.data_ptr(), _stream_handle(stream), cands.data_ptr(),
-                                    ncand.data_ptr(), ctypes.byref(off))
+        fn = load().sps_stream_push_graph if graph else load().sps_stream_push
+        rc = fn(self._h, gulp.data_ptr(), _stream_handle(stream), cands.data_ptr(), ncand.data_ptr(),
+                ctypes.byref(off))
         if rc:
-            raise SpsError(rc, "sps_stream_push")
+            raise SpsError(rc, "sps_stream_push_graph" if graph else "sps_stream_push")
         return int(off.value)
 
     def flush(self, cands, ncand, stream=None) -> int:

@@ -111,3 +111,47 @@ def test_stream_workload_rows_full_length():
     sel = np.isin(got["dm_idx"], rows)
     assert compare_cands(got[sel], ref, b.snr_thresh, "c3-rows") == 0
     assert exact_equal(got[sel], ref)
+
+
+def test_graph_gulp_step_matches_eager_every_replay():
+    # The captured gulp step is replayed once per gulp from a fixed input
+    # buffer refilled by eager copies; every replay must equal the eager push.
+    import torch
+    m = sps()
+    b = synth.Block(ndm=6, nsamp=10 * 2048, max_width=512, baseline_len=3000, seed=31, n_pulses=10,
+                    pulse_width=(1, 256), pulse_snr=(6.0, 25.0), straddle_period=2048)
+    x = synth.generate(b)
+    gulp = 2048
+    ref = oracle.search(x, 512, 3000, 5.0)
+    with m.Plan(6, gulp, 512, 3000, 5.0) as pe, m.Plan(6, gulp, 512, 3000, 5.0) as pg:
+        ce, ne = pe.alloc_cands()
+        cg, ng = pg.alloc_cands()
+        se, sg = m.Stream(pe), m.Stream(pg)
+        buf = torch.empty((6, gulp), dtype=torch.float32, device="cuda")
+        out = []
+        for g in range(x.shape[1] // gulp):
+            print("graph replay %d" % g, flush=True)
+            buf.copy_(torch.from_numpy(np.ascontiguousarray(x[:, g * gulp:(g + 1) * gulp])))
+            off_g = sg.push(buf, cg, ng, graph=True)
+            torch.cuda.synchronize()
+            got_g = m.cands_to_numpy(cg, ng, pg.max_cands)
+            off_e = se.push(buf, ce, ne)
+            torch.cuda.synchronize()
+            got_e = m.cands_to_numpy(ce, ne, pe.max_cands)
+            assert off_g == off_e == g * gulp
+            assert exact_equal(got_g, got_e), "replay %d differs from the eager push" % g
+            a = np.empty(got_g.size, dtype=oracle.CAND_DTYPE)
+            a["sample"] = got_g["sample"].astype(np.int64) + off_g
+            a["dm_idx"], a["width"], a["snr"] = got_g["dm_idx"], got_g["width"], got_g["snr"]
+            out.append(a)
+        end = sg.flush(cg, ng)
+        torch.cuda.synchronize()
+        last = m.cands_to_numpy(cg, ng, pg.max_cands)
+        a = np.empty(last.size, dtype=oracle.CAND_DTYPE)
+        a["sample"] = last["sample"].astype(np.int64) + end
+        a["dm_idx"], a["width"], a["snr"] = last["dm_idx"], last["width"], last["snr"]
+        out.append(a)
+        se.close()
+        sg.close()
+    got = oracle.sort_cands(np.concatenate(out))
+    assert exact_equal(got, ref)
