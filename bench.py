@@ -66,6 +66,7 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=[1, 2])
     ap.add_argument("--cpu-rows", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip timing the plain per-stage path")
     ap.add_argument("--mode", default="search", choices=["search", "copy"],
                     help="copy: time a plain device-to-device copy of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -126,6 +127,23 @@ def main():
     n = int(ncand.item())
     log("timed %d steps: %.3f ms/step, %d candidates" % (args.steps, (t1 - t0) * 1e3 / args.steps, n))
 
+    # the plain per-stage path on the same input (comparison only, not the metric)
+    plain_ms = None
+    if not args.no_plain:
+        plan.search(xd, cands, ncand, stream=stream, plain=True)
+        torch.cuda.synchronize()
+        n_plain = int(ncand.item())
+        plan.timing_read()
+        tp0 = time.perf_counter()
+        for i in range(max(1, args.steps // 2)):
+            plan.search(xd, cands, ncand, stream=stream, plain=True)
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - tp0) * 1e3 / max(1, args.steps // 2)
+        pst, pn = plan.timing_read()
+        log("plain per-stage path: %.3f ms/step (%d candidates)" % (plain_ms, n_plain))
+        if n_plain != n:
+            raise SystemExit("plain and fused candidate counts differ: %d vs %d" % (n_plain, n))
+
     samples = b.ndm * b.nsamp
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = samples * args.steps / (t1 - t0)
@@ -156,7 +174,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "path_hbm_frac": 4.0 * value / 1e9 / HBM_PEAK_GBS,
-        "stages_ms": {k: round(v, 4) for k, v in avg.items()},
+        "stages_ms": {k: round(v, 4) for k, v in avg.items() if k != "plain"},
+        "plain_ms_per_step": plain_ms,
+        "fused_vs_plain": (plain_ms / ms_per_step) if plain_ms else None,
         "candidates": n,
         "cpu_baseline": cpu,
     }

@@ -392,8 +392,58 @@ int sps_search(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand*
 }
 
 int sps_search_plain(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand) {
-  (void)p; (void)d_series; (void)stream; (void)d_cands; (void)d_ncand;
-  return fail(SPS_ERR_INVALID_ARG);  // provided by the per-stage path (sps_plain.hip)
+  if (!p || !d_series || !d_ncand || (!d_cands && p->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+  const int strip = 4096;  // positions per wave in the peak stage
+  const int nstrip = (p->nsamp + strip - 1) / strip;
+  const size_t n = (size_t)p->ndm * p->nsamp;
+  const size_t bytes_r = n * 4, bytes_p = (size_t)p->ndm * (p->nsamp + 1) * 4, bytes_s = n * 4, bytes_f = n,
+               bytes_frag = (size_t)p->ndm * nstrip * sizeof(sps::RunSum);
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t need = al(bytes_r) + al(bytes_p) + al(bytes_s) + al(bytes_f) + al(bytes_frag);
+  if (p->plain_bytes < need) {
+    if (p->d_plain) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(p->d_plain);
+      p->d_plain = nullptr;
+      p->plain_bytes = 0;
+    }
+    if (hipMalloc(&p->d_plain, need) != hipSuccess) {
+      (void)hipGetLastError();
+      p->d_plain = nullptr;
+      return fail(SPS_ERR_OOM);
+    }
+    p->plain_bytes = need;
+  }
+  char* w = static_cast<char*>(p->d_plain);
+  sps::PlainArgs a;
+  a.x = d_series;
+  a.N = p->nsamp;
+  a.nblocks = p->nblocks;
+  a.rows = p->ndm;
+  a.med = p->d_med;
+  a.mad = p->d_mad;
+  a.r = reinterpret_cast<int32_t*>(w); w += al(bytes_r);
+  a.P = reinterpret_cast<uint32_t*>(w); w += al(bytes_p);
+  a.S = reinterpret_cast<int32_t*>(w); w += al(bytes_s);
+  a.flag = reinterpret_cast<uint8_t*>(w); w += al(bytes_f);
+  a.frag = reinterpret_cast<sps::RunSum*>(w);
+  a.strip = strip;
+  a.nstrip = nstrip;
+  a.theta = (double)p->thresh;
+  a.cands = d_cands;
+  a.ncand = d_ncand;
+  a.cap = (uint32_t)p->max_cands;
+  hipEvent_t e0 = mark(p, stream);
+  if (sps::launch_zero_u32(d_ncand, 1, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  if (launch_stats(p, d_series, stream, p->d_med, p->d_mad) != SPS_OK) return g_last_error;
+  if (sps::launch_plain_prepare(a, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  for (int j = 0; j < p->nw; ++j) {
+    a.w = 1 << j;
+    a.sqrtw = p->sqrtw[j];
+    if (sps::launch_plain_width(a, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  }
+  span(p, 3, e0, mark(p, stream));
+  return ok();
 }
 
 }  // extern "C"

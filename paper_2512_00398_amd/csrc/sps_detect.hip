@@ -30,6 +30,7 @@
 #include <type_traits>
 
 #include "sps_internal.h"
+#include "sps_runs.h"
 #include "sps_wave.h"
 
 namespace sps {
@@ -39,97 +40,6 @@ namespace {
 constexpr int kC = 1024;                 // samples (window ends) per step
 constexpr int kRing = 8192;              // ring entries, >= kC + 64 + max width
 constexpr int kGroups = kC / 64;         // 64-position groups per step and width
-constexpr int kCbuf = 64;                // LDS candidate staging records per buffer
-
-struct Emitter {
-  sps_cand* cbuf;       // LDS staging (null: write to global directly)
-  uint32_t* cbuf_n;
-  sps_cand* cands;
-  uint32_t* ncand;
-  uint32_t cap;
-  uint32_t dm;
-  uint32_t width;
-  bool writer;          // the one thread that writes (lane 0 in wave code)
-  int32_t soff;         // emitted sample = position - soff
-};
-
-__device__ __forceinline__ void emit(const Emitter& E, int32_t sample, int32_t S, double den) {
-  if (!E.writer) return;
-  sps_cand c;
-  c.sample = sample - E.soff;
-  c.dm_idx = E.dm;
-  c.width = E.width;
-  c.snr = (float)((double)S / den);
-  if (E.cbuf) {
-    const uint32_t s = atomicAdd(E.cbuf_n, 1u);
-    if (s < (uint32_t)kCbuf) {
-      E.cbuf[s] = c;
-      return;
-    }
-  }
-  const uint32_t slot = atomicAdd(E.ncand, 1u);
-  if (slot < E.cap) E.cands[slot] = c;
-}
-
-__device__ __forceinline__ RunSum rs_empty() {
-  RunSum r;
-  r.flags = 0; r.hi = 0; r.ti = 0; r.hS = 0; r.tS = 0; r.pad = 0; r.hd = 1.0; r.td = 1.0;
-  return r;
-}
-
-// true if S1/d1 at i1 beats S2/d2 at i2 in the rounded-double order (larger
-// S/N, earlier sample on ties). S > 0 and d > 0 for every above position.
-__device__ __forceinline__ bool beats(int S1, double d1, int i1, int S2, double d2, int i2) {
-  if (d1 == d2) return S1 > S2 || (S1 == S2 && i1 < i2);
-  const double a = (double)S1 * d2, b = (double)S2 * d1;
-  // a, b carry < 2^-53 relative error each: a gap of 1e-15 proves the
-  // rounded quotients differ in the same direction
-  if (a > b * (1.0 + 1e-15)) return true;
-  if (a < b * (1.0 - 1e-15)) return false;
-  const double q1 = (double)S1 / d1, q2 = (double)S2 / d2;
-  return q1 > q2 || (q1 == q2 && i1 < i2);
-}
-
-// Summary of range L followed immediately by range R. Runs that end at the
-// junction (and so touch neither end of L+R) are emitted.
-__device__ RunSum rs_combine(const RunSum& L, const RunSum& R, const Emitter& E) {
-  if (!(L.flags & kNonEmpty)) return R;
-  if (!(R.flags & kNonEmpty)) return L;
-  RunSum o = rs_empty();
-  o.flags = kNonEmpty;
-  if (L.flags & kFull) {
-    o.flags |= kHead;
-    o.hi = L.hi; o.hS = L.hS; o.hd = L.hd;
-    if ((R.flags & kHead) && beats(R.hS, R.hd, R.hi, o.hS, o.hd, o.hi)) { o.hi = R.hi; o.hS = R.hS; o.hd = R.hd; }
-    if (R.flags & kFull) { o.flags |= kFull; return o; }
-    if (R.flags & kTail) { o.flags |= kTail; o.ti = R.ti; o.tS = R.tS; o.td = R.td; }
-    return o;
-  }
-  if (L.flags & kHead) { o.flags |= kHead; o.hi = L.hi; o.hS = L.hS; o.hd = L.hd; }
-  if (R.flags & kFull) {
-    o.flags |= kTail;
-    o.ti = R.hi; o.tS = R.hS; o.td = R.hd;
-    if ((L.flags & kTail) && !beats(R.hS, R.hd, R.hi, L.tS, L.td, L.ti)) { o.ti = L.ti; o.tS = L.tS; o.td = L.td; }
-    return o;
-  }
-  if (R.flags & kTail) { o.flags |= kTail; o.ti = R.ti; o.tS = R.tS; o.td = R.td; }
-  const bool lt = L.flags & kTail, rh = R.flags & kHead;
-  if (lt && rh) {
-    if (beats(R.hS, R.hd, R.hi, L.tS, L.td, L.ti)) emit(E, R.hi, R.hS, R.hd);
-    else emit(E, L.ti, L.tS, L.td);
-  } else if (lt) {
-    emit(E, L.ti, L.tS, L.td);
-  } else if (rh) {
-    emit(E, R.hi, R.hS, R.hd);
-  }
-  return o;
-}
-
-// Runs touching the ends of a whole row are closed there.
-__device__ void rs_close(const RunSum& s, const Emitter& E) {
-  if (s.flags & kHead) emit(E, s.hi, s.hS, s.hd);
-  if (s.flags & kTail) emit(E, s.ti, s.tS, s.td);
-}
 
 // Best (largest S, earliest lane) of the lanes in `run`; wave-uniform result.
 __device__ __forceinline__ void run_best(uint64_t run, int S, int lane, int& bestS, int& bestLane) {
@@ -186,7 +96,7 @@ __device__ __forceinline__ int group_shift(int w) {
 //   D  (no barrier) owner waves fold step c into their widths' summaries
 // Samples, medians and MADs are fetched one step ahead of their use.
 template <int NW, bool VIRT>
-__global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
+__device__ __forceinline__ void detect_body(const DetectArgs& A, const int task) {
   const int nw = NW > 0 ? NW : A.nw;
   __shared__ uint32_t ring[kRing];
   __shared__ int32_t tlo[kMaxWidths][kGroups];
@@ -201,8 +111,8 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
 
   const int tid = threadIdx.x, lane = lane_id();
   const int wave = readfirst(tid >> 6);
-  const int row = blockIdx.x / A.nseg;
-  const int seg = blockIdx.x - row * A.nseg;
+  const int row = task / A.nseg;
+  const int seg = task - row * A.nseg;
   const int N = A.N;
   const int s0 = A.seg_base + seg * A.seg_len;
   const int s1 = min(N, s0 + A.seg_len);
@@ -290,19 +200,10 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
       carryP += tot;
     }
     if (tthr) {
-      const double den = (kMadToSigma * (double)cur_mad) * tsq;
-      int lo = INT_MAX, hi = INT_MAX;
-      if (cur_mad > 0) {
-        const double tt = A.theta * den;
-        if (tt < 2147483648.0) {
-          lo = (int)(floor(tt) - 1.0);
-          const double hd = ceil(tt) + 1.0;
-          hi = hd >= 2147483647.0 ? INT_MAX : (int)hd;
-        }
-      }
-      tlo[tj][tg] = lo;
-      thi[tj][tg] = hi;
-      tden[tj][tg] = cur_mad > 0 ? den : 1.0;
+      const Bound bd = make_bound(cur_mad, tsq, A.theta);
+      tlo[tj][tg] = bd.lo;
+      thi[tj][tg] = bd.hi;
+      tden[tj][tg] = bd.den;
     }
     if (c + 1 < nsteps) next_mad = fetch_mad(c + 1);
     if (tid == 0) step_mask = 0u;
@@ -387,11 +288,14 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
         const int e0 = eg + 64 * q, g = 4 * wave + q;
         const int e = e0 + lane;
         const int S = (int)(ring[e & (kRing - 1)] - ring[(e - w) & (kRing - 1)]);
-        const int lo = readfirst(tlo[j][g]), hi = readfirst(thi[j][g]);
-        const double d = tden[j][g];
-        const bool above = S > lo && ((S >= hi && hi != INT_MAX) || (double)S / d > A.theta);
+        Bound bd;
+        bd.lo = readfirst(tlo[j][g]);
+        bd.hi = readfirst(thi[j][g]);
+        bd.den = tden[j][g];
+        const double d = bd.den;
+        const bool is_above = above(S, bd, A.theta);
         const uint64_t V = lane_range(vlo - e0, vhi - e0);
-        const uint64_t M = ballot(above) & V;
+        const uint64_t M = ballot(is_above) & V;
         const RunSum gs = group_summary(M, V, S, d, s0 + e0 - w, lane, em);
         acc = rs_combine(acc, gs, em);
       }
@@ -448,6 +352,30 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
   __syncthreads();
   for (uint32_t i = tid; i < flush_n; i += 256)
     if (flush_base + i < A.cap) A.cands[flush_base + i] = cbuf[lb][i];
+}
+
+template <int NW, bool VIRT>
+__global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
+  detect_body<NW, VIRT>(A, blockIdx.x);
+}
+
+// Persistent form over a batch of blocks: workgroups take (item, segment)
+// tasks from a queue (items ordered by segment length, longest first) until
+// none is left; every workgroup leaves once the counter passes the total.
+template <int NW>
+__global__ __launch_bounds__(256) void k_detect_batch(BatchDetect B) {
+  __shared__ int s_task;
+  while (true) {
+    if (threadIdx.x == 0) s_task = (int)atomicAdd(B.counter, 1u);
+    __syncthreads();
+    const int task = s_task;
+    __syncthreads();
+    if (task >= B.total) break;
+    int it = 0;
+    while (it + 1 < B.nitems && B.offs[it + 1] <= task) ++it;
+    detect_body<NW, false>(B.items[it], task - B.offs[it]);
+    __syncthreads();
+  }
 }
 
 // Stitch the segment summaries of each (row, width) in order.

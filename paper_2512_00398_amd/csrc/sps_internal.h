@@ -110,6 +110,42 @@ struct StreamArgs {
   uint32_t cap;
 };
 
+// Plain per-stage path: every intermediate lives in device memory.
+struct PlainArgs {
+  const float* x;      // [rows][N]
+  int32_t N, nblocks, rows;
+  const int32_t* med;  // [rows][nblocks]
+  const int32_t* mad;
+  int32_t* r;          // [rows][N] residuals
+  uint32_t* P;         // [rows][N + 1] prefix sums
+  int32_t* S;          // [rows][N] boxcar sums of the current width
+  uint8_t* flag;       // [rows][N] threshold decisions of the current width
+  RunSum* frag;        // [rows][nstrip] strip summaries of the current width
+  int32_t strip, nstrip;
+  int32_t w;
+  double sqrtw, theta;
+  sps_cand* cands;
+  uint32_t* ncand;
+  uint32_t cap;
+};
+
+// Batch of independent searches: workgroups of one persistent launch take
+// tasks from a queue. Task t belongs to item i with offs[i] <= t < offs[i+1];
+// items are ordered by the cost of one task, largest first.
+struct BatchStats {
+  const StatsArgs* items;  // device array [nitems]
+  const int32_t* offs;     // device array [nitems + 1]: first chain of each item
+  int32_t nitems, total;
+  uint32_t* counter;       // device queue head, zero before the launch
+};
+
+struct BatchDetect {
+  const DetectArgs* items;
+  const int32_t* offs;     // first (row, segment) task of each item
+  int32_t nitems, total;
+  uint32_t* counter;
+};
+
 // Host-side launchers (defined in the .hip files).
 hipError_t launch_block_stats(const StatsArgs& a, int hist_bins, hipStream_t s);
 hipError_t launch_detect(const DetectArgs& a, hipStream_t s);
@@ -118,5 +154,7 @@ hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 hipError_t launch_stream_fold(const StreamArgs& a, hipStream_t s);
 hipError_t launch_stream_advance(const StreamArgs& a, hipStream_t s);
 hipError_t launch_stream_close(const StreamArgs& a, hipStream_t s);
+hipError_t launch_plain_prepare(const PlainArgs& a, hipStream_t s);
+hipError_t launch_plain_width(const PlainArgs& a, hipStream_t s);
 
 }  // namespace sps

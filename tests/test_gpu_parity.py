@@ -111,6 +111,15 @@ def test_edge_cases(name, x, w, L, theta):
     assert exact_equal(got, ref)
     got2, _, _ = check(x.astype(np.float32), w, L, theta, name + "-seg", detect_seg=1024, stats_seg=64)
     assert exact_equal(got2, ref)
+    got3, _, _ = check(x.astype(np.float32), w, L, theta, name + "-plain", plain=True)
+    assert exact_equal(got3, ref)
+
+
+def test_plain_per_stage_path_small_config():
+    cfg = synth.config(1)["blocks"][0]
+    x = synth.generate(cfg)
+    got, ref, ex = check(x, cfg.max_width, cfg.baseline_len, cfg.snr_thresh, "c1-plain", plain=True)
+    assert ex == 0 and exact_equal(got, ref)
 
 
 def test_histogram_span_variant():
@@ -146,6 +155,27 @@ def test_invalid_arguments_are_rejected():
                  (4, 100, 4, 0, 6.0), (4, 100, 4, 70000, 6.0), (4, 100, 4, 10, 0.0), (4, 100, 4, 10, float("nan"))]:
         with pytest.raises(m.SpsError):
             m.Plan(*args)
+
+
+def test_large_config_plain_equals_fused():
+    # Full single-large-file workload: the per-stage path and the fused path
+    # must produce identical candidate sets (every row, every width).
+    cfg = synth.config(2)["blocks"][0]
+    torch = _torch()
+    m = sps()
+    print("case c2 plain vs fused: generate", flush=True)
+    xd = to_dev(synth.generate(cfg))
+    with m.Plan(cfg.ndm, cfg.nsamp, cfg.max_width, cfg.baseline_len, cfg.snr_thresh) as p:
+        cands, ncand = p.alloc_cands()
+        p.search(xd, cands, ncand)
+        torch.cuda.synchronize()
+        fused = m.cands_to_numpy(cands, ncand, p.max_cands)
+        print("case c2: plain search", flush=True)
+        p.search(xd, cands, ncand, plain=True)
+        torch.cuda.synchronize()
+        plain = m.cands_to_numpy(cands, ncand, p.max_cands)
+    assert fused.size > 1000000
+    assert exact_equal(fused, plain)
 
 
 def test_large_config_sampled_rows():
