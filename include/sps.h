@@ -67,7 +67,7 @@ typedef struct {
 
 typedef struct sps_plan sps_plan;
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define SPS_BLOCK_STRIDE 64          /* S: samples per baseline block */
 #define SPS_MAX_WIDTH_LIMIT 4096     /* largest boxcar width */
 #define SPS_MAX_BASELINE_LEN 65535   /* largest baseline window L */
@@ -190,6 +190,49 @@ int sps_stream_state_size(const sps_stream* s, uint64_t* bytes);
 int sps_stream_save(sps_stream* s, hipStream_t stream, void* host_buf, uint64_t bytes);
 int sps_stream_restore(sps_stream* s, hipStream_t stream, const void* host_buf, uint64_t bytes);
 void sps_stream_destroy(sps_stream* s);
+
+/*
+ * Batch: many independent blocks ("files": the paper processes file after
+ * file, Section V; every block is searched exactly as sps_search would search
+ * it alone) in one persistent launch per stage. Workgroups take work from a
+ * device queue shared by all blocks, whose tasks are ordered largest first,
+ * so blocks of very different shapes load-balance with no per-block launch
+ * tail.
+ *
+ * sps_batch_item: one block. d_series device FP32 [ndm][nsamp] (caller-owned,
+ *   read-only); parameters obey the sps_plan_create rules; d_cands (capacity
+ *   max_cands records; may be NULL when max_cands is 0) and d_ncand are that
+ *   block's own outputs, exactly as for sps_search.
+ * sps_batch_create: an empty batch context (workspace grows on demand).
+ * sps_batch_search: enqueue the search of n items on `stream`. Asynchronous,
+ *   except that a call which needs more workspace than any earlier call (the
+ *   first one, for instance) first waits for the context's earlier work.
+ *   Item descriptors are copied during the call; the caller's array can be
+ *   reused on return. One stream at a time per context (calls on different
+ *   streams are ordered after the context's previous call). Returns SPS_OK or
+ *   SPS_ERR_INVALID_ARG (any item invalid: nothing enqueued), SPS_ERR_OOM,
+ *   SPS_ERR_HIP.
+ * sps_batch_set: tuning attributes SPS_ATTR_STATS_SEG, SPS_ATTR_DETECT_SEG,
+ *   SPS_ATTR_HIST_BINS (same meaning as for plans; apply to every item).
+ * sps_batch_destroy: waits for the context's work and frees it (NULL-safe).
+ */
+typedef struct {
+  const float* d_series;
+  int32_t ndm;
+  int32_t max_width;
+  int64_t nsamp;
+  int32_t baseline_len;
+  float snr_thresh;
+  sps_cand* d_cands;
+  uint32_t* d_ncand;
+  int64_t max_cands;
+} sps_batch_item;
+
+typedef struct sps_batch sps_batch;
+int sps_batch_create(sps_batch** out);
+int sps_batch_set(sps_batch* b, int attr, int64_t value);
+int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipStream_t stream);
+void sps_batch_destroy(sps_batch* b);
 
 /* Last error code of the calling thread, and a static text for a code. */
 int sps_last_error(void);

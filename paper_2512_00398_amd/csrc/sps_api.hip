@@ -1,4 +1,5 @@
 // sps_api.hip - the C interface of libsps: plans, argument checks, launches.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -811,6 +812,326 @@ int sps_stream_restore(sps_stream* s, hipStream_t stream, const void* host_buf, 
     return fail(SPS_ERR_HIP);
   if (hipMemcpy(s->tmin, &h.tmin, sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) return fail(SPS_ERR_HIP);
   s->pushed = h.pushed;
+  return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batch of independent blocks: one persistent launch per stage.
+
+struct sps_batch {
+  int device;
+  int32_t stats_seg, detect_seg, hist_bins;
+  int32_t* d_ms;       // medians then MADs of every item
+  int64_t ms_cap;      // int32 records
+  sps::RunSum* d_frag;
+  int64_t frag_cap;
+  char* d_tab;         // item descriptors, task offsets, counter pointers, queue heads
+  char* h_tab;         // pinned staging of d_tab
+  size_t tab_cap;
+  hipEvent_t uploaded; // h_tab may be rewritten once this has completed
+  hipEvent_t done;     // end of the last call's work
+  bool pending;        // both events recorded at least once
+  int grid_stats[2];   // resident workgroups: 4096 / 16384 bins (0 = not queried)
+  int grid_detect[2];  // 13 widths / any
+};
+
+namespace {
+
+struct BatchShape {
+  int idx;
+  int32_t nblocks, nw;
+  int32_t stats_seg, stats_nseg;
+  int32_t detect_seg, detect_nseg;
+  int64_t ms_off, frag_off;
+};
+
+bool item_valid(const sps_batch_item& it) {
+  return it.d_series && it.d_ncand && it.ndm >= 1 && it.nsamp >= 1 && it.nsamp <= (int64_t)INT32_MAX - 8192 &&
+         is_pow2(it.max_width) && it.max_width <= SPS_MAX_WIDTH_LIMIT && it.baseline_len >= 1 &&
+         it.baseline_len <= SPS_MAX_BASELINE_LEN && std::isfinite(it.snr_thresh) && it.snr_thresh > 0.0f &&
+         it.max_cands >= 0 && it.max_cands <= (int64_t)UINT32_MAX && (it.d_cands || it.max_cands == 0);
+}
+
+size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+template <class T>
+int grow(T** p, int64_t* cap, int64_t need) {
+  if (need <= *cap) return SPS_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  if (hipMalloc(reinterpret_cast<void**>(p), (size_t)need * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return SPS_ERR_OOM;
+  }
+  *cap = need;
+  return SPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sps_batch_create(sps_batch** out) {
+  if (!out) return fail(SPS_ERR_INVALID_ARG);
+  *out = nullptr;
+  sps_batch* b = new (std::nothrow) sps_batch;
+  if (!b) return fail(SPS_ERR_OOM);
+  std::memset(b, 0, sizeof(*b));
+  b->hist_bins = 4096;
+  if (hipGetDevice(&b->device) != hipSuccess ||
+      hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+    delete b;
+    return fail(SPS_ERR_HIP);
+  }
+  *out = b;
+  return ok();
+}
+
+int sps_batch_set(sps_batch* b, int attr, int64_t v) {
+  if (!b) return fail(SPS_ERR_INVALID_ARG);
+  switch (attr) {
+    case SPS_ATTR_STATS_SEG:
+      if (v < 0 || v > INT32_MAX) return fail(SPS_ERR_INVALID_ARG);
+      b->stats_seg = (int32_t)v;
+      return ok();
+    case SPS_ATTR_DETECT_SEG:
+      if (v < 0 || v > INT32_MAX || v % kDetectStep) return fail(SPS_ERR_INVALID_ARG);
+      b->detect_seg = (int32_t)v;
+      return ok();
+    case SPS_ATTR_HIST_BINS:
+      if (v != 4096 && v != 16384) return fail(SPS_ERR_INVALID_ARG);
+      b->hist_bins = (int32_t)v;
+      return ok();
+    default:
+      return fail(SPS_ERR_INVALID_ARG);
+  }
+}
+
+void sps_batch_destroy(sps_batch* b) {
+  if (!b) return;
+  if (b->pending) (void)hipEventSynchronize(b->done);
+  if (b->d_ms) (void)hipFree(b->d_ms);
+  if (b->d_frag) (void)hipFree(b->d_frag);
+  if (b->d_tab) (void)hipFree(b->d_tab);
+  if (b->h_tab) (void)hipHostFree(b->h_tab);
+  (void)hipEventDestroy(b->uploaded);
+  (void)hipEventDestroy(b->done);
+  delete b;
+}
+
+int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipStream_t stream) {
+  if (!b || n < 0 || (n > 0 && !items)) return fail(SPS_ERR_INVALID_ARG);
+  if (n == 0) return ok();
+  for (int32_t i = 0; i < n; ++i)
+    if (!item_valid(items[i])) return fail(SPS_ERR_INVALID_ARG);
+
+  // Shapes. Chain and segment lengths follow the single-block rules, sized
+  // for the whole batch so that the queue holds many more tasks than there
+  // are resident workgroups.
+  std::vector<BatchShape> sh((size_t)n);
+  int64_t total_blocks = 0, total_samples = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    total_blocks += (int64_t)items[i].ndm * ((items[i].nsamp + sps::kStride - 1) / sps::kStride);
+    total_samples += (int64_t)items[i].ndm * items[i].nsamp;
+  }
+  int64_t ms_need = 0, frag_need = 0, fix_total = 0;
+  bool all13 = true;
+  for (int32_t i = 0; i < n; ++i) {
+    const sps_batch_item& it = items[i];
+    BatchShape& s = sh[(size_t)i];
+    s.idx = i;
+    s.nblocks = (int32_t)((it.nsamp + sps::kStride - 1) / sps::kStride);
+    s.nw = 0;
+    for (int w = 1; w <= it.max_width; w <<= 1) ++s.nw;
+    all13 = all13 && s.nw == sps::kMaxWidths;
+    int64_t seg;
+    if (b->stats_seg > 0) {
+      seg = b->stats_seg;
+    } else {
+      seg = (total_blocks + 10239) / 10240;
+      seg = std::max<int64_t>(seg, std::max<int64_t>(64, (4LL * it.baseline_len + 63) / 64));
+    }
+    seg = std::max<int64_t>(1, std::min<int64_t>(seg, s.nblocks));
+    s.stats_seg = (int32_t)seg;
+    s.stats_nseg = (int32_t)((s.nblocks + seg - 1) / seg);
+    int64_t dseg = b->detect_seg > 0 ? b->detect_seg : std::max<int64_t>(total_samples / 4096, 4LL * it.max_width);
+    dseg = (dseg + kDetectStep - 1) / kDetectStep * kDetectStep;
+    const int64_t nmax = std::max<int64_t>(kDetectStep, (it.nsamp + kDetectStep - 1) / kDetectStep * kDetectStep);
+    dseg = std::max<int64_t>(kDetectStep, std::min<int64_t>(dseg, nmax));
+    s.detect_seg = (int32_t)dseg;
+    s.detect_nseg = (int32_t)((it.nsamp + dseg - 1) / dseg);
+    s.ms_off = ms_need;
+    ms_need += 2LL * it.ndm * s.nblocks;
+    s.frag_off = frag_need;
+    if (s.detect_nseg > 1) {
+      frag_need += (int64_t)it.ndm * s.nw * s.detect_nseg;
+      fix_total += (int64_t)it.ndm * s.nw;
+    }
+  }
+  // task counts must fit the int32 queue
+  int64_t stats_total = 0, detect_total = 0;
+  for (const BatchShape& s : sh) {
+    stats_total += (int64_t)items[s.idx].ndm * s.stats_nseg;
+    detect_total += (int64_t)items[s.idx].ndm * s.detect_nseg;
+  }
+  if (stats_total > INT32_MAX / 2 || detect_total > INT32_MAX / 2 || fix_total > INT32_MAX / 2)
+    return fail(SPS_ERR_INVALID_ARG);
+
+  // Table layout.
+  const size_t off_sa = 0;
+  const size_t off_da = align16(off_sa + (size_t)n * sizeof(sps::StatsArgs));
+  const size_t off_so = align16(off_da + (size_t)n * sizeof(sps::DetectArgs));
+  const size_t off_do = align16(off_so + (size_t)(n + 1) * sizeof(int32_t));
+  const size_t off_fo = align16(off_do + (size_t)(n + 1) * sizeof(int32_t));
+  const size_t off_np = align16(off_fo + (size_t)(n + 1) * sizeof(int32_t));
+  const size_t off_ct = align16(off_np + (size_t)n * sizeof(uint32_t*));
+  const size_t tab_bytes = align16(off_ct + 2 * sizeof(uint32_t));
+
+  // Workspace: growing waits for the context's earlier work.
+  if (ms_need > b->ms_cap || frag_need > b->frag_cap || tab_bytes > b->tab_cap) {
+    if (b->pending && hipEventSynchronize(b->done) != hipSuccess) return fail(SPS_ERR_HIP);
+    if (grow(&b->d_ms, &b->ms_cap, ms_need) != SPS_OK) return fail(SPS_ERR_OOM);
+    if (frag_need > 0 && grow(&b->d_frag, &b->frag_cap, frag_need) != SPS_OK) return fail(SPS_ERR_OOM);
+    if (tab_bytes > b->tab_cap) {
+      if (b->d_tab) (void)hipFree(b->d_tab);
+      if (b->h_tab) (void)hipHostFree(b->h_tab);
+      b->d_tab = nullptr;
+      b->h_tab = nullptr;
+      b->tab_cap = 0;
+      const size_t cap = std::max<size_t>(tab_bytes, 64 * 1024);
+      if (hipMalloc(reinterpret_cast<void**>(&b->d_tab), cap) != hipSuccess ||
+          hipHostMalloc(reinterpret_cast<void**>(&b->h_tab), cap, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SPS_ERR_OOM);
+      }
+      b->tab_cap = cap;
+    }
+  }
+  const int bins = b->hist_bins == 16384 ? 1 : 0;
+  if (!b->grid_stats[bins]) b->grid_stats[bins] = sps::block_stats_batch_grid(b->hist_bins);
+  if (!b->grid_detect[all13 ? 0 : 1]) b->grid_detect[all13 ? 0 : 1] = sps::detect_batch_grid(all13 ? 13 : 0);
+  if (b->grid_stats[bins] <= 0 || b->grid_detect[all13 ? 0 : 1] <= 0) return fail(SPS_ERR_HIP);
+
+  // Order after the previous call (possibly on another stream), and wait
+  // until the staging buffer is free again.
+  if (b->pending) {
+    if (hipStreamWaitEvent(stream, b->done, 0) != hipSuccess) return fail(SPS_ERR_HIP);
+    if (hipEventSynchronize(b->uploaded) != hipSuccess) return fail(SPS_ERR_HIP);
+  }
+
+  char* h = b->h_tab;
+  char* d = b->d_tab;
+  auto* sa = reinterpret_cast<sps::StatsArgs*>(h + off_sa);
+  auto* da = reinterpret_cast<sps::DetectArgs*>(h + off_da);
+  auto* so = reinterpret_cast<int32_t*>(h + off_so);
+  auto* dof = reinterpret_cast<int32_t*>(h + off_do);
+  auto* fo = reinterpret_cast<int32_t*>(h + off_fo);
+  auto* np = reinterpret_cast<uint32_t**>(h + off_np);
+
+  // Stats queue: longest chains (warm-up window + segment) first.
+  std::vector<BatchShape> ord = sh;
+  std::stable_sort(ord.begin(), ord.end(), [&](const BatchShape& x, const BatchShape& y) {
+    const int64_t cx = x.stats_seg + std::min<int64_t>(items[x.idx].baseline_len, items[x.idx].nsamp) / 64;
+    const int64_t cy = y.stats_seg + std::min<int64_t>(items[y.idx].baseline_len, items[y.idx].nsamp) / 64;
+    return cx > cy;
+  });
+  int32_t acc = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    const BatchShape& s = ord[(size_t)k];
+    const sps_batch_item& it = items[s.idx];
+    sps::StatsArgs& a = sa[k];
+    std::memset(&a, 0, sizeof(a));
+    a.x = it.d_series;
+    a.ld = it.nsamp;
+    a.N = (int32_t)it.nsamp;
+    a.L = it.baseline_len;
+    a.nblocks = s.nblocks;
+    a.kb_first = 0;
+    a.seg_blocks = s.stats_seg;
+    a.nseg = s.stats_nseg;
+    a.nchains = it.ndm * s.stats_nseg;
+    a.tmin = nullptr;
+    a.med = b->d_ms + s.ms_off;
+    a.mad = b->d_ms + s.ms_off + (int64_t)it.ndm * s.nblocks;
+    so[k] = acc;
+    acc += a.nchains;
+  }
+  so[n] = acc;
+
+  // Detect queue: longest segments (segment + widest halo) first; the fix-up
+  // reads the same table.
+  ord = sh;
+  std::stable_sort(ord.begin(), ord.end(), [&](const BatchShape& x, const BatchShape& y) {
+    const int64_t cx = std::min<int64_t>(x.detect_seg, items[x.idx].nsamp) + items[x.idx].max_width;
+    const int64_t cy = std::min<int64_t>(y.detect_seg, items[y.idx].nsamp) + items[y.idx].max_width;
+    return cx > cy;
+  });
+  acc = 0;
+  int32_t facc = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    const BatchShape& s = ord[(size_t)k];
+    const sps_batch_item& it = items[s.idx];
+    sps::DetectArgs& a = da[k];
+    std::memset(&a, 0, sizeof(a));
+    a.x = it.d_series;
+    a.ld = it.nsamp;
+    a.N = (int32_t)it.nsamp;
+    a.nblocks = s.nblocks;
+    a.nw = s.nw;
+    a.maxw = it.max_width;
+    a.med = b->d_ms + s.ms_off;
+    a.mad = b->d_ms + s.ms_off + (int64_t)it.ndm * s.nblocks;
+    a.theta = (double)it.snr_thresh;
+    for (int j = 0; j < s.nw; ++j) a.sqrtw[j] = std::sqrt((double)(1 << j));
+    a.seg_base = 0;
+    a.seg_len = s.detect_seg;
+    a.nseg = s.detect_nseg;
+    a.rows = it.ndm;
+    a.e_first = 0;
+    a.tmin = nullptr;
+    a.sample_offset = 0;
+    a.keep_edges = 0;
+    a.row_offset = 0;
+    a.cands = it.d_cands;
+    a.ncand = it.d_ncand;
+    a.cap = (uint32_t)it.max_cands;
+    a.frag = s.detect_nseg > 1 ? b->d_frag + s.frag_off : nullptr;
+    dof[k] = acc;
+    acc += it.ndm * s.detect_nseg;
+    fo[k] = facc;
+    if (s.detect_nseg > 1) facc += it.ndm * s.nw;
+  }
+  dof[n] = acc;
+  fo[n] = facc;
+  for (int32_t i = 0; i < n; ++i) np[i] = items[i].d_ncand;
+
+  if (hipMemcpyAsync(d, h, tab_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipEventRecord(b->uploaded, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+
+  uint32_t* counters = reinterpret_cast<uint32_t*>(d + off_ct);
+  sps::BatchStats bs{reinterpret_cast<const sps::StatsArgs*>(d + off_sa), reinterpret_cast<const int32_t*>(d + off_so),
+                     n, so[n], counters};
+  sps::BatchDetect bd{reinterpret_cast<const sps::DetectArgs*>(d + off_da),
+                      reinterpret_cast<const int32_t*>(d + off_do), n, dof[n], counters + 1};
+  const int wpg = b->hist_bins == 16384 ? 2 : 4;
+  const int gs = (int)std::min<int64_t>(b->grid_stats[bins], (bs.total + wpg - 1) / wpg);
+  const int gd = (int)std::min<int64_t>(b->grid_detect[all13 ? 0 : 1], bd.total);
+  if (sps::launch_batch_zero(reinterpret_cast<uint32_t* const*>(d + off_np), n, counters, stream) != hipSuccess ||
+      sps::launch_block_stats_batch(bs, b->hist_bins, gs, stream) != hipSuccess ||
+      sps::launch_detect_batch(bd, all13 ? 13 : 0, gd, stream) != hipSuccess ||
+      sps::launch_fixup_batch(bd, reinterpret_cast<const int32_t*>(d + off_fo), fo[n], stream) != hipSuccess ||
+      hipEventRecord(b->done, stream) != hipSuccess) {
+    b->pending = true;
+    return fail(SPS_ERR_HIP);
+  }
+  b->pending = true;
   return ok();
 }
 

@@ -368,7 +368,7 @@ __global__ __launch_bounds__(256) void k_detect_batch(BatchDetect B) {
   while (true) {
     if (threadIdx.x == 0) s_task = (int)atomicAdd(B.counter, 1u);
     __syncthreads();
-    const int task = s_task;
+    const int task = __builtin_amdgcn_readfirstlane(s_task);
     __syncthreads();
     if (task >= B.total) break;
     int it = 0;
@@ -379,9 +379,7 @@ __global__ __launch_bounds__(256) void k_detect_batch(BatchDetect B) {
 }
 
 // Stitch the segment summaries of each (row, width) in order.
-__global__ __launch_bounds__(256) void k_fixup(DetectArgs A) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= A.rows * A.nw) return;
+__device__ __forceinline__ void fixup_one(const DetectArgs& A, const int t) {
   const int row = t / A.nw, j = t - row * A.nw;
   const Emitter em{nullptr, nullptr, A.cands, A.ncand, A.cap, (uint32_t)row + A.row_offset, (uint32_t)(1 << j),
                    true, A.sample_offset};
@@ -389,6 +387,32 @@ __global__ __launch_bounds__(256) void k_fixup(DetectArgs A) {
   RunSum acc = rs_empty();
   for (int s = 0; s < A.nseg; ++s) acc = rs_combine(acc, f[s], em);
   rs_close(acc, em);
+}
+
+__global__ __launch_bounds__(256) void k_fixup(DetectArgs A) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= A.rows * A.nw) return;
+  fixup_one(A, t);
+}
+
+// Batch: thread t -> (item, row, width); items with one segment per row
+// contribute no threads (their runs were closed by the detect kernel).
+__global__ __launch_bounds__(256) void k_fixup_batch(BatchDetect B, const int32_t* offs) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= offs[B.nitems]) return;
+  int lo = 0, hi = B.nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  fixup_one(B.items[lo], t - offs[lo]);
+}
+
+// Batch prologue: zero every item's candidate counter and both queue heads.
+__global__ __launch_bounds__(256) void k_batch_zero(uint32_t* const* ncand, int n, uint32_t* counters) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) *ncand[t] = 0u;
+  if (t < 2) counters[t] = 0u;
 }
 
 __device__ __forceinline__ RunSum rs_shift(RunSum r, int d) {
@@ -499,6 +523,35 @@ hipError_t launch_stream_advance(const StreamArgs& a, hipStream_t s) {
   if (a.rows <= 0) return hipSuccess;
   const int chunks = (a.Hx + 4095) / 4096;
   hipLaunchKernelGGL(k_stream_advance, dim3(chunks > 0 ? chunks : 1, a.rows), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_detect_batch(const BatchDetect& b, int nw_all, int grid, hipStream_t s) {
+  if (b.total <= 0) return hipSuccess;
+  if (nw_all == 13) hipLaunchKernelGGL((k_detect_batch<13>), dim3(grid), dim3(256), 0, s, b);
+  else hipLaunchKernelGGL((k_detect_batch<0>), dim3(grid), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+int detect_batch_grid(int nw_all) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  hipError_t e = nw_all == 13 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_detect_batch<13>, 256, 0)
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_detect_batch<0>, 256, 0);
+  if (e != hipSuccess) return 0;
+  return cus * (per > 0 ? per : 1);
+}
+
+hipError_t launch_fixup_batch(const BatchDetect& b, const int32_t* d_offs, int total, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fixup_batch, dim3((total + 255) / 256), dim3(256), 0, s, b, d_offs);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_zero(uint32_t* const* d_ncand, int n, uint32_t* counters, hipStream_t s) {
+  const int m = n > 2 ? n : 2;
+  hipLaunchKernelGGL(k_batch_zero, dim3((m + 255) / 256), dim3(256), 0, s, d_ncand, n, counters);
   return hipGetLastError();
 }
 

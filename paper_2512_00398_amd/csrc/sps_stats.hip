@@ -292,15 +292,8 @@ __device__ __forceinline__ void chain_step(Chain<NB, VIRT>& c, int lo, int hi, b
 // WPG chains (waves) per workgroup; LDS = WPG * NB * 2 bytes. Blocks
 // [kb_first, nblocks) of every row are computed; windows never reach below
 // the device value *tmin (the first sample of a stream).
-template <int NB, int WPG, bool VIRT>
-__global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
-  __shared__ uint32_t hist[WPG][NB / 2];
-  // wave index kept in a VGPR: the chain state then stays on the vector unit,
-  // which measures faster than moving its bookkeeping to the shared scalar unit
-  const int wave = threadIdx.x >> 6;
-  const int lane = lane_id();
-  const int chain = blockIdx.x * WPG + wave;
-  if (chain >= a.nchains) return;  // whole wave leaves; no block barriers are used
+template <int NB, bool VIRT>
+__device__ __forceinline__ void stats_chain(const StatsArgs& a, const int chain, uint32_t* H, const int lane) {
   const int row = chain / a.nseg;
   const int seg = chain - row * a.nseg;
   const int kb0 = a.kb_first + seg * a.seg_blocks;
@@ -308,7 +301,7 @@ __global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
   const int N = a.N, L = a.L;
   const int t0 = a.tmin ? *a.tmin : 0;
   Chain<NB, VIRT> c;
-  c.H = hist[wave];
+  c.H = H;
   c.row.g = a.x + (int64_t)row * a.ld;
   c.row.h = VIRT ? a.hist + (int64_t)row * a.ldh : nullptr;
   c.row.Hx = VIRT ? a.Hx : 0;
@@ -351,6 +344,35 @@ __global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
   }
 }
 
+template <int NB, int WPG, bool VIRT>
+__global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
+  __shared__ uint32_t hist[WPG][NB / 2];
+  // wave index kept in a VGPR: the chain state then stays on the vector unit,
+  // which measures faster than moving its bookkeeping to the shared scalar unit
+  const int wave = threadIdx.x >> 6;
+  const int chain = blockIdx.x * WPG + wave;
+  if (chain >= a.nchains) return;  // whole wave leaves; no block barriers are used
+  stats_chain<NB, VIRT>(a, chain, hist[wave], lane_id());
+}
+
+// Persistent form over a batch: every wave takes chains from the queue on its
+// own (no block barriers) until the counter passes the total.
+template <int NB, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_block_stats_batch(BatchStats B) {
+  __shared__ uint32_t hist[WPG][NB / 2];
+  const int wave = threadIdx.x >> 6;
+  const int lane = lane_id();
+  while (true) {
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(B.counter, 1u);
+    const int task = __builtin_amdgcn_readfirstlane((int)t);
+    if (task >= B.total) break;
+    int it = 0;
+    while (it + 1 < B.nitems && B.offs[it + 1] <= task) ++it;
+    stats_chain<NB, false>(B.items[it], task - B.offs[it], hist[wave], lane);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_block_stats(const StatsArgs& a, int hist_bins, hipStream_t s) {
@@ -364,6 +386,24 @@ hipError_t launch_block_stats(const StatsArgs& a, int hist_bins, hipStream_t s) 
     else hipLaunchKernelGGL((k_block_stats<4096, 4, false>), dim3((a.nchains + 3) / 4), dim3(256), 0, s, a);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_block_stats_batch(const BatchStats& b, int hist_bins, int grid, hipStream_t s) {
+  if (b.total <= 0) return hipSuccess;
+  if (hist_bins == 16384) hipLaunchKernelGGL((k_block_stats_batch<16384, 2>), dim3(grid), dim3(128), 0, s, b);
+  else hipLaunchKernelGGL((k_block_stats_batch<4096, 4>), dim3(grid), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+int block_stats_batch_grid(int hist_bins) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  hipError_t e = hist_bins == 16384
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_block_stats_batch<16384, 2>, 128, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_block_stats_batch<4096, 4>, 256, 0);
+  if (e != hipSuccess) return 0;
+  return cus * (per > 0 ? per : 1);
 }
 
 }  // namespace sps

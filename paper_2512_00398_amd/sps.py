@@ -54,6 +54,10 @@ EXPORTS = [
     ("sps_stream_save", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64]),
     ("sps_stream_restore", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64]),
     ("sps_stream_destroy", None, [_P]),
+    ("sps_batch_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p)]),
+    ("sps_batch_set", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64]),
+    ("sps_batch_search", ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
+    ("sps_batch_destroy", None, [_P]),
     ("sps_last_error", ctypes.c_int, []),
     ("sps_error_string", ctypes.c_char_p, [ctypes.c_int]),
 ]
@@ -253,6 +257,65 @@ class Stream:
     def close(self) -> None:
         if getattr(self, "_h", None):
             load().sps_stream_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class BatchItem(ctypes.Structure):
+    """sps_batch_item (include/sps.h)."""
+    _fields_ = [("d_series", ctypes.c_void_p), ("ndm", ctypes.c_int32), ("max_width", ctypes.c_int32),
+                ("nsamp", ctypes.c_int64), ("baseline_len", ctypes.c_int32), ("snr_thresh", ctypes.c_float),
+                ("d_cands", ctypes.c_void_p), ("d_ncand", ctypes.c_void_p), ("max_cands", ctypes.c_int64)]
+
+
+assert ctypes.sizeof(BatchItem) == 56
+
+
+class Batch:
+    """Many independent blocks searched by one persistent launch per stage (see include/sps.h)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        rc = load().sps_batch_create(ctypes.byref(h))
+        if rc:
+            raise SpsError(rc, "sps_batch_create")
+        self._h = h.value
+
+    def set(self, attr: int, value: int) -> None:
+        rc = load().sps_batch_set(self._h, int(attr), int(value))
+        if rc:
+            raise SpsError(rc, "sps_batch_set")
+
+    def search(self, items, stream=None) -> None:
+        """items: sequence of (series, max_width, baseline_len, snr_thresh, cands, ncand).
+
+        series is a contiguous float32 [ndm][nsamp] GPU tensor; cands an
+        int32 [capacity][4] GPU tensor (capacity = its first dimension);
+        ncand an int32 GPU tensor of one element."""
+        arr = (BatchItem * max(1, len(items)))()
+        for k, (x, w, L, th, cands, ncand) in enumerate(items):
+            ndm, nsamp = x.shape
+            _check_series(x, ndm, nsamp)
+            arr[k] = BatchItem(x.data_ptr(), int(ndm), int(w), int(nsamp), int(L), float(th),
+                               cands.data_ptr(), ncand.data_ptr(), int(cands.shape[0]))
+        rc = load().sps_batch_search(self._h, ctypes.cast(arr, ctypes.c_void_p), len(items), _stream_handle(stream))
+        if rc:
+            raise SpsError(rc, "sps_batch_search")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().sps_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

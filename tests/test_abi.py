@@ -45,6 +45,10 @@ def test_null_plan_calls_fail_cleanly():
     v = ctypes.c_int64()
     assert lib.sps_plan_get(None, sps.ATTR_MAX_CANDS, ctypes.byref(v)) == sps.SPS_ERR_INVALID_ARG
     lib.sps_plan_destroy(None)
+    assert lib.sps_batch_create(None) == sps.SPS_ERR_INVALID_ARG
+    assert lib.sps_batch_set(None, sps.ATTR_STATS_SEG, 64) == sps.SPS_ERR_INVALID_ARG
+    assert lib.sps_batch_search(None, None, 0, None) == sps.SPS_ERR_INVALID_ARG
+    lib.sps_batch_destroy(None)
     assert sps.error_string(0) == "success"
     assert "overflow" in sps.error_string(sps.SPS_ERR_OVERFLOW)
 
