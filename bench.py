@@ -132,16 +132,83 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def bench_serve(args):
+    """Serving workload: 16 beams, Poisson gulp arrivals at 1.5x real time,
+    admission against the memory budget; gulp latency percentiles at the
+    literal rate and over a time-compressed sweep up to saturation."""
+    import torch
+    import synth
+    from paper_2512_00398_amd import serve
+
+    cfg = synth.config(5)
+    blocks = cfg["blocks"]
+    G = 2  # distinct gulps held per beam, replayed in turn
+    pools = []
+    for b in blocks:
+        x = synth.generate(b.with_(nsamp=G * b.nsamp))
+        pools.append(torch.from_numpy(x.reshape(b.ndm, G, b.nsamp).transpose(1, 0, 2).copy()).cuda())
+        del x
+    specs = [serve.BeamSpec(ndm=b.ndm, nsamp=b.nsamp, max_width=b.max_width, baseline_len=b.baseline_len,
+                            snr_thresh=b.snr_thresh) for b in blocks]
+    log("serving %d beams, %.3g samples per round of gulps" % (len(specs), sum(s.ndm * s.nsamp for s in specs)))
+
+    def source(beam, k):
+        return pools[beam][k % G]
+
+    rate = cfg["arrival_rate_x_realtime"]
+    budget = cfg["hbm_budget_bytes"]
+    seed = synth.BASE_SEED + 4
+
+    def run(compress, **kw):
+        arr = serve.poisson_arrivals(specs, rate, seed, **kw)
+        ex = serve.GpuExecutor(source, nstreams=4, cand_cap=1 << 23)
+        rep = serve.serve(specs, arr, ex, budget, compress=compress)
+        s = rep.summary()
+        s["compress"] = "inf" if compress == float("inf") else compress
+        s["offered_samples_per_s"] = (sum(specs[a.beam].ndm * specs[a.beam].nsamp for a in arr) /
+                                      (max(a.t for a in arr) / compress) if compress != float("inf") else None)
+        s["ncand_total"] = int(sum(r.ncand for r in rep.records))
+        log("serve x%s: %s" % (s["compress"], {k: s[k] for k in ("gulps", "p50_ms", "p99_ms", "samples_per_s")}))
+        return s
+
+    for _ in range(max(1, args.warmup)):
+        run(float("inf"), gulps_per_beam=2)
+    literal = run(1.0, horizon=args.serve_horizon)
+    sweep = [run(c, gulps_per_beam=6) for c in (10.0, 30.0, 60.0, 120.0, float("inf"))]
+    if len({s["ncand_total"] for s in sweep}) != 1:
+        raise SystemExit("candidate totals differ between serving runs of the same gulps: %s" %
+                         [s["ncand_total"] for s in sweep])
+    sat = sweep[-1]
+    out = {
+        "metric": "DM-trial-samples/s", "value": sat["samples_per_s"], "unit": "DM-trial-samples/s", "n_gpus": 1,
+        "steps": sat["gulps"], "warmup": args.warmup, "ms_per_step": sat["wall_s"] * 1e3 / sat["gulps"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+        "config": {"workload": "%s: 16 beams, ndm 512..2048, gulps 2^16..2^18, widths=1..4096, baseline=16384, "
+                               "theta=6, Poisson arrivals at %.1fx real time, budget %d B" %
+                               (cfg["name"], rate, budget),
+                   "value_is": "saturation throughput (all arrivals at once), gulp = step"},
+        "latency_literal_rate": literal,
+        "latency_sweep": sweep,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 4],
-                    help="1 small block, 2 single large block (default), 4 batch of 32 files")
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 4, 5],
+                    help="1 small block, 2 single large block (default), 4 batch of 32 files, "
+                         "5 serving 16 beams (literal arrival rate, then a time-compressed sweep)")
+    ap.add_argument("--serve-horizon", type=float, default=20.0,
+                    help="seconds of literal-rate arrivals served in --config 5")
     ap.add_argument("--cpu-rows", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain per-stage path")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the plan's speed-only attributes on the input first (untimed; cached as JSON)")
     ap.add_argument("--mode", default="search", choices=["search", "copy"],
                     help="copy: time a plain device-to-device copy of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -168,6 +235,8 @@ def main():
 
     if args.config == 4:
         return bench_batch(args)
+    if args.config == 5:
+        return bench_serve(args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -188,6 +257,11 @@ def main():
     del x
     stream = torch.cuda.current_stream()
     plan = sps.Plan(b.ndm, b.nsamp, b.max_width, b.baseline_len, b.snr_thresh)
+    tuned = None
+    if args.autotune:
+        from paper_2512_00398_amd import autotune
+        tuned = autotune.tune(plan, xd, stream=stream, steps=2, log=log)
+        log("autotune: %s (%.3f ms, default %.3f ms)" % (tuned["config"], tuned["ms"], tuned["default_ms"]))
     cands, ncand = plan.alloc_cands()
     for i in range(args.warmup):
         plan.search(xd, cands, ncand, stream=stream)
@@ -256,6 +330,7 @@ def main():
         "plain_ms_per_step": plain_ms,
         "fused_vs_plain": (plain_ms / ms_per_step) if plain_ms else None,
         "candidates": n,
+        "tuning": tuned["config"] if tuned else "library defaults",
         "cpu_baseline": cpu,
     }
     plan.close()

@@ -234,6 +234,17 @@ int sps_batch_set(sps_batch* b, int attr, int64_t value);
 int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipStream_t stream);
 void sps_batch_destroy(sps_batch* b);
 
+/*
+ * Device memory a plan of this shape holds with default tuning (and, with
+ * streaming = 1, a stream on it as well), in bytes; nothing is allocated and
+ * no device is needed. Inputs and candidate buffers are the caller's and not
+ * counted. For admission control against a memory budget. Returns SPS_OK or
+ * SPS_ERR_INVALID_ARG (the shape would be rejected by sps_plan_create or
+ * sps_stream_create).
+ */
+int sps_footprint(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baseline_len, int streaming,
+                  uint64_t* bytes);
+
 /* Last error code of the calling thread, and a static text for a code. */
 int sps_last_error(void);
 const char* sps_error_string(int code);

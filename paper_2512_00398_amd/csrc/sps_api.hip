@@ -122,10 +122,14 @@ void span(sps_plan* p, int stage, hipEvent_t a, hipEvent_t b) {
 }
 
 // Make room for the run summaries of multi-segment rows (host-synchronous).
-int ensure_frag(sps_plan* p) {
+int64_t frag_need(const sps_plan* p) {
   const int64_t seg = auto_detect_seg(p);
   const int64_t nseg = (p->nsamp + seg - 1) / seg;
-  const int64_t need = nseg > 1 ? (int64_t)p->ndm * p->nw * nseg : 0;
+  return nseg > 1 ? (int64_t)p->ndm * p->nw * nseg : 0;
+}
+
+int ensure_frag(sps_plan* p) {
+  const int64_t need = frag_need(p);
   if (need <= p->frag_cap) return SPS_OK;
   if (p->d_frag) {
     (void)hipDeviceSynchronize();
@@ -485,6 +489,29 @@ struct StreamHeader {
 };
 constexpr uint64_t kStreamMagic = 0x5350535354524D31ull;  // "SPSSTRM1"
 
+// History length, virtual row and detection segments of a stream on plan p.
+bool stream_geometry(const sps_plan* p, sps_stream* s) {
+  const int64_t need = std::max<int64_t>(p->baseline_len, p->max_width);
+  s->Hx = (int32_t)((need + kDetectStep - 1) / kDetectStep * kDetectStep);
+  s->Hb = s->Hx / sps::kStride;
+  s->nbv = s->Hb + p->nsamp / sps::kStride;
+  if ((int64_t)s->Hx + p->nsamp > (int64_t)INT32_MAX - 8192) return false;
+  s->Nv = s->Hx + p->nsamp;
+  // positions of a push are those whose window ends inside the gulp
+  int64_t first = (int64_t)s->Hx + 1 - p->max_width;
+  if (first < 0) first = 0;
+  s->seg_base = (int32_t)(first / kDetectStep * kDetectStep);
+  s->seg_len = detect_seg_for(p, s->Nv - s->seg_base);
+  s->nseg = (s->Nv - s->seg_base + s->seg_len - 1) / s->seg_len;
+  return true;
+}
+
+uint64_t stream_device_bytes(const sps_stream* s) {
+  const sps_plan* p = s->plan;
+  return 2ull * ((uint64_t)p->ndm * s->Hx * sizeof(float) + 2ull * p->ndm * s->nbv * sizeof(int32_t)) +
+         (uint64_t)p->ndm * p->nw * (1 + s->nseg) * sizeof(sps::RunSum) + sizeof(int32_t);
+}
+
 uint64_t stream_state_bytes(const sps_stream* s) {
   const sps_plan* p = s->plan;
   return sizeof(StreamHeader) + (uint64_t)p->ndm * s->Hx * sizeof(float) +
@@ -563,21 +590,10 @@ int sps_stream_create(sps_plan* p, sps_stream** out) {
   if (!s) return fail(SPS_ERR_OOM);
   std::memset(s, 0, sizeof(*s));
   s->plan = p;
-  const int64_t need = std::max<int64_t>(p->baseline_len, p->max_width);
-  s->Hx = (int32_t)((need + kDetectStep - 1) / kDetectStep * kDetectStep);
-  s->Hb = s->Hx / sps::kStride;
-  s->nbv = s->Hb + p->nsamp / sps::kStride;
-  if ((int64_t)s->Hx + p->nsamp > (int64_t)INT32_MAX - 8192) {
+  if (!stream_geometry(p, s)) {
     delete s;
     return fail(SPS_ERR_INVALID_ARG);
   }
-  s->Nv = s->Hx + p->nsamp;
-  // positions of a push are those whose window ends inside the gulp
-  int64_t first = (int64_t)s->Hx + 1 - p->max_width;
-  if (first < 0) first = 0;
-  s->seg_base = (int32_t)(first / kDetectStep * kDetectStep);
-  s->seg_len = detect_seg_for(p, s->Nv - s->seg_base);
-  s->nseg = (s->Nv - s->seg_base + s->seg_len - 1) / s->seg_len;
   bool okm = true;
   for (int i = 0; i < 2 && okm; ++i) {
     okm = hipMalloc(&s->hist[i], (size_t)p->ndm * s->Hx * sizeof(float)) == hipSuccess &&
@@ -812,6 +828,36 @@ int sps_stream_restore(sps_stream* s, hipStream_t stream, const void* host_buf, 
     return fail(SPS_ERR_HIP);
   if (hipMemcpy(s->tmin, &h.tmin, sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) return fail(SPS_ERR_HIP);
   s->pushed = h.pushed;
+  return ok();
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int sps_footprint(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baseline_len, int streaming,
+                  uint64_t* bytes) {
+  if (!bytes || ndm < 1 || nsamp < 1 || nsamp > (int64_t)INT32_MAX - 8192 || !is_pow2(max_width) ||
+      max_width > SPS_MAX_WIDTH_LIMIT || baseline_len < 1 || baseline_len > SPS_MAX_BASELINE_LEN ||
+      (streaming && nsamp % sps::kStride != 0))
+    return fail(SPS_ERR_INVALID_ARG);
+  sps_plan p;
+  std::memset(&p, 0, sizeof(p));
+  p.ndm = ndm;
+  p.nsamp = (int32_t)nsamp;
+  p.max_width = max_width;
+  p.baseline_len = baseline_len;
+  p.nblocks = (int32_t)((nsamp + sps::kStride - 1) / sps::kStride);
+  for (int w = 1; w <= max_width; w <<= 1) ++p.nw;
+  uint64_t total = 2ull * ndm * p.nblocks * sizeof(int32_t) + (uint64_t)frag_need(&p) * sizeof(sps::RunSum);
+  if (streaming) {
+    sps_stream s;
+    std::memset(&s, 0, sizeof(s));
+    s.plan = &p;
+    if (!stream_geometry(&p, &s)) return fail(SPS_ERR_INVALID_ARG);
+    total += stream_device_bytes(&s);
+  }
+  *bytes = total;
   return ok();
 }
 

@@ -1,0 +1,300 @@
+"""Serving loop: many beams streamed concurrently on one GPU.
+
+Each beam is one long observation arriving gulp by gulp (the paper's
+real-time setting: chunks of a continuous stream searched as they arrive,
+Sections III-B and V-C). A beam owns a plan and a device-resident stream
+(history, block statistics and open runs are carried between its gulps), so a
+beam's results are those of searching its whole observation at once.
+
+The scheduler is plain host logic and runs against any executor:
+
+- Admission: a beam is admitted when its device footprint (plan + stream +
+  input and candidate buffers) fits in what is left of the memory budget;
+  otherwise it waits, first come first served, until admitted beams finish.
+- Dispatch: every arriving gulp of an admitted beam is enqueued at once
+  (continuous: no batch is formed or waited for). A beam's gulps stay in order
+  on the device stream the beam is bound to; beams are spread over a few
+  device streams so that gulps of different beams overlap on the GPU.
+- Latency of a gulp: from its arrival to the completion of its search on the
+  device (candidates in device memory).
+
+GpuExecutor does the device work through the HIP library; a test may pass any
+object with the same methods.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import sps
+
+
+@dataclasses.dataclass(frozen=True)
+class BeamSpec:
+    ndm: int
+    nsamp: int                # samples per gulp (multiple of 64)
+    max_width: int = 4096
+    baseline_len: int = 16384
+    snr_thresh: float = 6.0
+    tsamp: float = 64e-6      # seconds per sample (sets the real-time gulp period)
+
+    @property
+    def gulp_seconds(self) -> float:
+        return self.nsamp * self.tsamp
+
+
+@dataclasses.dataclass(frozen=True)
+class Arrival:
+    t: float                  # seconds after the start of the run (before time compression)
+    beam: int
+    k: int                    # gulp index within the beam
+
+
+def poisson_arrivals(specs: Sequence[BeamSpec], rate_x_realtime: float, seed: int,
+                     gulps_per_beam: Optional[int] = None, horizon: Optional[float] = None) -> List[Arrival]:
+    """Poisson arrivals per beam, mean inter-arrival = gulp duration / rate.
+
+    Stops each beam after `gulps_per_beam` gulps and/or at time `horizon`."""
+    if gulps_per_beam is None and horizon is None:
+        raise ValueError("give gulps_per_beam or horizon")
+    out: List[Arrival] = []
+    for b, s in enumerate(specs):
+        rng = np.random.default_rng([seed, b])
+        mean = s.gulp_seconds / rate_x_realtime
+        t, k = 0.0, 0
+        while True:
+            t += float(rng.exponential(mean))
+            if (gulps_per_beam is not None and k >= gulps_per_beam) or (horizon is not None and t > horizon):
+                break
+            out.append(Arrival(t, b, k))
+            k += 1
+    out.sort(key=lambda a: (a.t, a.beam, a.k))
+    return out
+
+
+class Admission:
+    """First-come-first-served admission against a byte budget."""
+
+    def __init__(self, budget: int):
+        self.budget = int(budget)
+        self.used = 0
+        self.admitted: Dict[int, int] = {}
+        self.waiting: "collections.OrderedDict[int, int]" = collections.OrderedDict()
+
+    def enqueue(self, beam: int, nbytes: int) -> None:
+        if beam in self.admitted or beam in self.waiting:
+            return
+        if nbytes > self.budget:
+            raise ValueError("beam %d needs %d bytes, more than the whole budget %d" % (beam, nbytes, self.budget))
+        self.waiting[beam] = int(nbytes)
+
+    def drain(self) -> List[int]:
+        """Admit from the head of the waiting line while it fits; returns the beams admitted."""
+        got = []
+        while self.waiting:
+            beam, nbytes = next(iter(self.waiting.items()))
+            if self.used + nbytes > self.budget:
+                break
+            self.waiting.popitem(last=False)
+            self.admitted[beam] = nbytes
+            self.used += nbytes
+            got.append(beam)
+        return got
+
+    def release(self, beam: int) -> List[int]:
+        self.used -= self.admitted.pop(beam)
+        return self.drain()
+
+
+@dataclasses.dataclass
+class GulpRecord:
+    beam: int
+    k: int
+    arrival: float            # seconds (compressed clock)
+    submitted: float          # host seconds when enqueued
+    done: Optional[float] = None
+    ncand: Optional[int] = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclasses.dataclass
+class Report:
+    records: List[GulpRecord]
+    wall: float
+    samples: int
+    max_concurrent_bytes: int
+
+    def latencies(self) -> np.ndarray:
+        return np.array([r.latency for r in self.records], dtype=np.float64)
+
+    def summary(self) -> dict:
+        lat = self.latencies()
+        return {"gulps": len(self.records), "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+                "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+                "max_ms": float(lat.max() * 1e3) if lat.size else None, "wall_s": self.wall,
+                "samples_per_s": self.samples / self.wall if self.wall > 0 else None,
+                "max_admitted_bytes": self.max_concurrent_bytes}
+
+
+def serve(specs: Sequence[BeamSpec], arrivals: Sequence[Arrival], executor, budget: int, compress: float = 1.0,
+          clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep) -> Report:
+    """Run the arrivals through the executor; compress > 1 speeds the arrival clock up
+    (float('inf'): everything arrives at once)."""
+    left = collections.Counter(a.beam for a in arrivals)
+    adm = Admission(budget)
+    backlog: Dict[int, collections.deque] = collections.defaultdict(collections.deque)
+    records: List[GulpRecord] = []
+    inflight: Dict[int, GulpRecord] = {}
+    pending = collections.deque(sorted(arrivals, key=lambda a: (a.t, a.beam, a.k)))
+    state = {"max_used": 0, "samples": 0}
+    t0 = clock()
+    executor.start(t0)
+
+    def now() -> float:
+        return clock() - t0
+
+    def due(a: Arrival) -> float:
+        return 0.0 if compress == float("inf") else a.t / compress
+
+    def submit(a: Arrival, arrived: float) -> None:
+        rec = GulpRecord(a.beam, a.k, arrived, now())
+        executor.submit(rec, specs[a.beam])
+        inflight[id(rec)] = rec
+        state["samples"] += specs[a.beam].ndm * specs[a.beam].nsamp
+
+    def admit(beams: List[int]) -> None:
+        for b in beams:
+            executor.open(b, specs[b])
+            state["max_used"] = max(state["max_used"], adm.used)
+            while backlog[b]:
+                submit(*backlog[b].popleft())
+
+    while pending or inflight:
+        tn = now()
+        while pending and due(pending[0]) <= tn:
+            a = pending.popleft()
+            if a.beam in adm.admitted:
+                submit(a, due(a))
+            else:
+                backlog[a.beam].append((a, due(a)))
+                adm.enqueue(a.beam, executor.footprint(specs[a.beam]))
+                admit(adm.drain())
+        for rec in executor.poll():
+            del inflight[id(rec)]
+            records.append(rec)
+            left[rec.beam] -= 1
+            if left[rec.beam] == 0:
+                executor.close(rec.beam)
+                admit(adm.release(rec.beam))
+        if pending and not inflight:
+            sleep(max(0.0, min(due(pending[0]) - now(), 1e-3)))
+        elif inflight:
+            sleep(5e-5)
+    if any(backlog.values()) or adm.waiting:
+        raise RuntimeError("serving ended with gulps that were never admitted")
+    wall = now()
+    executor.stop()
+    records.sort(key=lambda r: (r.beam, r.k))
+    return Report(records, wall, state["samples"], state["max_used"])
+
+
+class GpuExecutor:
+    """Device work of the serving loop: one plan + stream per admitted beam.
+
+    gulp_source(beam, k) returns the device tensor [ndm][nsamp] of gulp k of
+    the beam. With keep=True every gulp's candidates are copied to the host
+    (global sample indices) for inspection; otherwise only counts are kept."""
+
+    def __init__(self, gulp_source: Callable[[int, int], "object"], nstreams: int = 4, cand_cap: int = 1 << 22,
+                 cand_slots: int = 2, keep: bool = False):
+        import torch
+        self.torch = torch
+        self.src = gulp_source
+        self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        self.cap = int(cand_cap)
+        self.slots = int(cand_slots)
+        self.keep = keep
+        self.beams: Dict[int, dict] = {}
+        self.waiting: List[Tuple[GulpRecord, object, object, object]] = []
+        self.kept: Dict[int, list] = collections.defaultdict(list)
+        self.ref = None
+
+    def footprint(self, s: BeamSpec) -> int:
+        return sps.footprint(s.ndm, s.nsamp, s.max_width, s.baseline_len, True) + self.slots * (16 * self.cap + 4)
+
+    def start(self, t0: float) -> None:
+        """t0: the scheduler's clock origin in time.perf_counter seconds."""
+        torch = self.torch
+        self.t0 = t0
+        self.ref = torch.cuda.Event(enable_timing=True)
+        self.ref.record(self.streams[0])
+        self.ref.synchronize()
+        self.t_ref = time.perf_counter()
+
+    def open(self, beam: int, s: BeamSpec) -> None:
+        torch = self.torch
+        plan = sps.Plan(s.ndm, s.nsamp, s.max_width, s.baseline_len, s.snr_thresh)
+        plan.set(sps.ATTR_MAX_CANDS, self.cap)
+        st = sps.Stream(plan)
+        bufs = [(torch.empty((self.cap, 4), dtype=torch.int32, device="cuda"),
+                 torch.zeros((1,), dtype=torch.int32, device="cuda")) for _ in range(self.slots)]
+        self.beams[beam] = {"plan": plan, "stream": st, "bufs": bufs, "hs": self.streams[beam % len(self.streams)],
+                            "n": 0, "spec": s}
+
+    def submit(self, rec: GulpRecord, s: BeamSpec) -> None:
+        torch = self.torch
+        b = self.beams[rec.beam]
+        hs = b["hs"]
+        x = self.src(rec.beam, rec.k)
+        cands, ncand = b["bufs"][b["n"] % self.slots]
+        b["n"] += 1
+        off = b["stream"].push(x, cands, ncand, stream=hs)
+        ev = torch.cuda.Event(enable_timing=True)   # search done: candidates in device memory
+        ev.record(hs)
+        host_n = torch.empty((1,), dtype=torch.int32, pin_memory=True)
+        with torch.cuda.stream(hs):
+            host_n.copy_(ncand, non_blocking=True)
+        copied = torch.cuda.Event()                  # count readable on the host
+        copied.record(hs)
+        if self.keep:
+            # wait for this gulp so its slot can be reused safely
+            copied.synchronize()
+            got = sps.cands_to_numpy(cands, ncand, self.cap)
+            self.kept[rec.beam].append((got, off))
+        self.waiting.append((rec, ev, copied, host_n))
+
+    def poll(self) -> List[GulpRecord]:
+        done = []
+        still = []
+        for item in self.waiting:
+            rec, ev, copied, host_n = item
+            if copied.query():
+                rec.done = self.t_ref - self.t0 + self.ref.elapsed_time(ev) * 1e-3
+                rec.ncand = int(host_n.item()) & 0xFFFFFFFF
+                if rec.ncand > self.cap:
+                    raise sps.SpsError(sps.SPS_ERR_OVERFLOW, "gulp %d of beam %d" % (rec.k, rec.beam))
+                done.append(rec)
+            else:
+                still.append(item)
+        self.waiting = still
+        return done
+
+    def close(self, beam: int) -> None:
+        b = self.beams.pop(beam)
+        cands, ncand = b["bufs"][b["n"] % self.slots]
+        end = b["stream"].flush(cands, ncand, stream=b["hs"])
+        b["hs"].synchronize()
+        if self.keep:
+            self.kept[beam].append((sps.cands_to_numpy(cands, ncand, self.cap), end))
+        b["stream"].close()
+        b["plan"].close()
+
+    def stop(self) -> None:
+        self.torch.cuda.synchronize()

@@ -54,6 +54,8 @@ EXPORTS = [
     ("sps_stream_save", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64]),
     ("sps_stream_restore", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64]),
     ("sps_stream_destroy", None, [_P]),
+    ("sps_footprint", ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_uint64)]),
     ("sps_batch_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p)]),
     ("sps_batch_set", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64]),
     ("sps_batch_search", ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
@@ -270,6 +272,16 @@ class Stream:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def footprint(ndm: int, nsamp: int, max_width: int, baseline_len: int, streaming: bool = False) -> int:
+    """Device bytes a plan (and a stream on it) of this shape holds; no device needed."""
+    v = ctypes.c_uint64()
+    rc = load().sps_footprint(int(ndm), int(nsamp), int(max_width), int(baseline_len), int(bool(streaming)),
+                              ctypes.byref(v))
+    if rc:
+        raise SpsError(rc, "sps_footprint")
+    return int(v.value)
 
 
 class BatchItem(ctypes.Structure):

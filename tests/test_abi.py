@@ -60,3 +60,17 @@ def test_binding_has_no_cpu_fallback():
     assert "oracle" not in src.replace("no CPU fallback", "")
     for f in os.listdir(os.path.join(ROOT, "paper_2512_00398_amd", "csrc")):
         assert "oracle" not in open(os.path.join(ROOT, "paper_2512_00398_amd", "csrc", f)).read().lower()
+
+
+def test_footprint_query_without_device():
+    from paper_2512_00398_amd import sps
+    # plan: medians + MADs (2 x ndm x ceil(N/64) int32) + segment summaries
+    base = sps.footprint(64, 16384, 64, 4096)
+    assert base >= 2 * 64 * 256 * 4
+    assert sps.footprint(128, 16384, 64, 4096) > base
+    # a stream adds at least two history buffers of ndm x max(L, w) samples
+    st = sps.footprint(64, 16384, 64, 4096, streaming=True)
+    assert st - base >= 2 * 64 * 4096 * 4
+    for bad in ((0, 16384, 64, 4096, False), (4, 100, 3, 10, False), (4, 100, 4, 10, True)):
+        with pytest.raises(sps.SpsError):
+            sps.footprint(*bad)
