@@ -179,10 +179,10 @@ int sps_stream_create(sps_plan* plan, sps_stream** out);
 int sps_stream_push(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand,
                     int64_t* gulp_offset);
 /* sps_stream_push_graph: the same gulp step replayed from a captured HIP
- * graph (one per history parity, captured on first use for a given
- * (d_gulp, d_cands, d_ncand) triple and kept until the triple changes):
- * pass a fixed, double-buffered input location. Same results as
- * sps_stream_push. */
+ * graph (one per history parity, captured on first use of a (d_gulp,
+ * d_cands, d_ncand) triple; the 8 most recently used triples are kept, so a
+ * fixed set of double- or triple-buffered input locations is captured once).
+ * Same results as sps_stream_push. */
 int sps_stream_push_graph(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands,
                           uint32_t* d_ncand, int64_t* gulp_offset);
 int sps_stream_flush(sps_stream* s, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand, int64_t* end_offset);

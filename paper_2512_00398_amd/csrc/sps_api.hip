@@ -456,6 +456,8 @@ int sps_search_plain(sps_plan* p, const float* d_series, hipStream_t stream, sps
 // ---------------------------------------------------------------------------
 // Streaming: gulp after gulp of one observation, the carried state on device.
 
+constexpr int kGraphCache = 8;
+
 struct sps_stream {
   sps_plan* plan;       // borrowed: gulp shape and tuning
   int32_t Hx;           // history samples kept per row (multiple of 1024)
@@ -472,10 +474,15 @@ struct sps_stream {
   sps::RunSum* frag;    // [ndm][nw][nseg]
   int32_t* tmin;        // device: virtual index of the stream's first sample (clamped at 0)
   int64_t pushed;       // samples pushed so far
-  // captured gulp steps, one per history parity, for one (gulp, cands, ncand) triple
+  // captured gulp steps, one per history parity, for each of a few recently
+  // used (gulp, cands, ncand) buffer triples (least recently used replaced)
   hipStream_t cap_stream;
-  hipGraphExec_t exec[2];
-  const void* exec_key[3];
+  struct GraphEntry {
+    const void* key[3];
+    hipGraphExec_t exec[2];
+    uint64_t last_use;
+  } graphs[kGraphCache];
+  uint64_t graph_clock;
 };
 
 namespace {
@@ -555,8 +562,9 @@ void stream_free(sps_stream* s) {
   if (s->carry) (void)hipFree(s->carry);
   if (s->frag) (void)hipFree(s->frag);
   if (s->tmin) (void)hipFree(s->tmin);
-  for (int i = 0; i < 2; ++i)
-    if (s->exec[i]) (void)hipGraphExecDestroy(s->exec[i]);
+  for (auto& e : s->graphs)
+    for (int i = 0; i < 2; ++i)
+      if (e.exec[i]) (void)hipGraphExecDestroy(e.exec[i]);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
 }
@@ -723,12 +731,25 @@ int sps_stream_push(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_
 int sps_stream_push_graph(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands,
                           uint32_t* d_ncand, int64_t* gulp_offset) {
   if (!s || !d_gulp || !d_ncand || (!d_cands && s->plan->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
-  if (s->exec_key[0] != d_gulp || s->exec_key[1] != d_cands || s->exec_key[2] != d_ncand) {
-    for (int i = 0; i < 2; ++i) {
-      if (s->exec[i]) (void)hipGraphExecDestroy(s->exec[i]);
-      s->exec[i] = nullptr;
+  sps_stream::GraphEntry* hit = nullptr;
+  for (auto& e : s->graphs)
+    if (e.exec[0] && e.key[0] == d_gulp && e.key[1] == d_cands && e.key[2] == d_ncand) hit = &e;
+  if (!hit) {
+    for (auto& e : s->graphs)
+      if (!e.exec[0]) {
+        hit = &e;
+        break;
+      }
+    if (!hit) {
+      hit = &s->graphs[0];
+      for (auto& e : s->graphs)
+        if (e.last_use < hit->last_use) hit = &e;
     }
-    s->exec_key[0] = s->exec_key[1] = s->exec_key[2] = nullptr;
+    for (int i = 0; i < 2; ++i) {
+      if (hit->exec[i]) (void)hipGraphExecDestroy(hit->exec[i]);
+      hit->exec[i] = nullptr;
+    }
+    hit->key[0] = hit->key[1] = hit->key[2] = nullptr;
     if (!s->cap_stream && hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess)
       return fail(SPS_ERR_HIP);
     for (int i = 0; i < 2; ++i) {
@@ -739,21 +760,26 @@ int sps_stream_push_graph(sps_stream* s, const float* d_gulp, hipStream_t stream
       if (rc != SPS_OK || ec != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
         (void)hipGetLastError();
+        if (hit->exec[0]) (void)hipGraphExecDestroy(hit->exec[0]);
+        hit->exec[0] = nullptr;
         return fail(SPS_ERR_HIP);
       }
-      const hipError_t ei = hipGraphInstantiate(&s->exec[i], g, nullptr, nullptr, 0);
+      const hipError_t ei = hipGraphInstantiate(&hit->exec[i], g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if (ei != hipSuccess) {
-        s->exec[i] = nullptr;
+        hit->exec[i] = nullptr;
+        if (hit->exec[0]) (void)hipGraphExecDestroy(hit->exec[0]);
+        hit->exec[0] = nullptr;
         (void)hipGetLastError();
         return fail(SPS_ERR_HIP);
       }
     }
-    s->exec_key[0] = d_gulp;
-    s->exec_key[1] = d_cands;
-    s->exec_key[2] = d_ncand;
+    hit->key[0] = d_gulp;
+    hit->key[1] = d_cands;
+    hit->key[2] = d_ncand;
   }
-  if (hipGraphLaunch(s->exec[s->cur], stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  hit->last_use = ++s->graph_clock;
+  if (hipGraphLaunch(hit->exec[s->cur], stream) != hipSuccess) return fail(SPS_ERR_HIP);
   if (gulp_offset) *gulp_offset = s->pushed;
   s->pushed += s->plan->nsamp;
   s->cur ^= 1;

@@ -155,3 +155,43 @@ def test_graph_gulp_step_matches_eager_every_replay():
         sg.close()
     got = oracle.sort_cands(np.concatenate(out))
     assert exact_equal(got, ref)
+
+
+def test_graph_rotating_buffers_equal_one_shot():
+    # Three input buffers and two candidate buffers in rotation: six buffer
+    # triples, each captured once and replayed; more triples than the cache
+    # holds once a fourth input buffer joins for the last gulps.
+    import torch
+    m = sps()
+    gulp, ng = 2048, 14
+    b = synth.Block(ndm=5, nsamp=ng * gulp, max_width=1024, baseline_len=2500, seed=57, n_pulses=12,
+                    pulse_width=(1, 512), pulse_snr=(6.0, 25.0), straddle_period=gulp)
+    x = synth.generate(b)
+    ref = oracle.search(x, 1024, 2500, 5.0)
+    out = []
+    with m.Plan(5, gulp, 1024, 2500, 5.0) as p:
+        bufs = [torch.empty((5, gulp), dtype=torch.float32, device="cuda") for _ in range(4)]
+        cb = [p.alloc_cands() for _ in range(3)]
+        st = m.Stream(p)
+        for g in range(ng):
+            xb = bufs[g % 3] if g < 10 else bufs[3 if g % 2 else g % 3]
+            c, n = cb[g % 2] if g < 12 else cb[2]
+            print("rotating graph push %d" % g, flush=True)
+            xb.copy_(torch.from_numpy(np.ascontiguousarray(x[:, g * gulp:(g + 1) * gulp])))
+            off = st.push(xb, c, n, graph=True)
+            torch.cuda.synchronize()
+            got = m.cands_to_numpy(c, n, p.max_cands)
+            a = np.empty(got.size, dtype=oracle.CAND_DTYPE)
+            a["sample"] = got["sample"].astype(np.int64) + off
+            a["dm_idx"], a["width"], a["snr"] = got["dm_idx"], got["width"], got["snr"]
+            out.append(a)
+        c, n = cb[0]
+        end = st.flush(c, n)
+        torch.cuda.synchronize()
+        last = m.cands_to_numpy(c, n, p.max_cands)
+        a = np.empty(last.size, dtype=oracle.CAND_DTYPE)
+        a["sample"] = last["sample"].astype(np.int64) + end
+        a["dm_idx"], a["width"], a["snr"] = last["dm_idx"], last["width"], last["snr"]
+        out.append(a)
+        st.close()
+    assert exact_equal(oracle.sort_cands(np.concatenate(out)), ref)
