@@ -41,48 +41,111 @@ constexpr int kC = 1024;                 // samples (window ends) per step
 constexpr int kRing = 8192;              // ring entries, >= kC + 64 + max width
 constexpr int kGroups = kC / 64;         // 64-position groups per step and width
 
-// Best (largest S, earliest lane) of the lanes in `run`; wave-uniform result.
-__device__ __forceinline__ void run_best(uint64_t run, int S, int lane, int& bestS, int& bestLane) {
-  const bool in = (run >> lane) & 1ull;
-  bestS = wave_max_u(in ? S : INT_MIN);
-  bestLane = ctz(ballot(in && S == bestS));
-}
-
-// Summary of one 64-position group with a single denominator d. M: above
-// lanes, V: valid lanes (contiguous), i0: sample index of lane 0.
-__device__ RunSum group_summary(uint64_t M, uint64_t V, int S, double d, int i0, int lane, const Emitter& E) {
-  RunSum g = rs_empty();
-  if (!V) return g;
-  g.flags = kNonEmpty;
-  if (!M) return g;
-  int bs, bl;
-  if (M == V) {
-    run_best(M, S, lane, bs, bl);
-    g.flags |= kFull | kHead;
-    g.hi = i0 + bl; g.hS = bs; g.hd = d;
-    return g;
-  }
-  const int fv = ctz(V), lv = msb(V);
-  uint64_t m = M;
-  while (m) {
-    const int a = ctz(m);
-    const uint64_t gap = ~m & (~0ull << a);
-    const int b = gap ? ctz(gap) : 64;
-    const uint64_t run = (b == 64 ? ~0ull : ((1ull << b) - 1ull)) & (~0ull << a);
-    run_best(run, S, lane, bs, bl);
-    if (a == fv) { g.flags |= kHead; g.hi = i0 + bl; g.hS = bs; g.hd = d; }
-    else if (b - 1 == lv) { g.flags |= kTail; g.ti = i0 + bl; g.tS = bs; g.td = d; }
-    else emit(E, i0 + bl, bs, d);
-    m &= ~run;
-  }
-  return g;
-}
-
 // Window ends of width w in a step start (64 - ceil(w/2) mod 64) mod 64
 // before the step, so that every 64-lane group shares one centre block.
 __device__ __forceinline__ int group_shift(int w) {
   const int sub = w - (w >> 1);
   return (64 - (sub & 63)) & 63;
+}
+
+// One level of the in-order combine of 16 group summaries held by the lanes
+// of a DPP row: lanes at multiples of 2D absorb the summary of lane + D.
+template <int D>
+__device__ __forceinline__ RunSum rs_absorb(const RunSum& g, int grp, bool act, const Emitter& em) {
+  RunSum r;
+  r.flags = row_down<D>(0, g.flags);
+  r.hi = row_down<D>(0, g.hi);
+  r.ti = row_down<D>(0, g.ti);
+  r.hS = row_down<D>(0, g.hS);
+  r.tS = row_down<D>(0, g.tS);
+  r.pad = 0;
+  r.hd = row_down<D>(1.0, g.hd);
+  r.td = row_down<D>(1.0, g.td);
+  const bool mine = (grp & (2 * D - 1)) == 0;
+  Emitter e = em;
+  e.writer = act && mine;
+  const RunSum c = rs_combine(g, r, e);
+  return mine ? c : g;
+}
+
+// Run pass of one step over its flagged widths. Lane (wave, l) takes group
+// l % 16 of the (4 * wave + l / 16)-th flagged width: the 64 window ends of
+// one centre block, scanned in order (so the group's best is the largest S,
+// earliest on ties), runs inside the group emitted at once. The 16 group
+// summaries of a width (one DPP row) are then combined in order; lane 0 of
+// the row leaves the step's summary of that width in wsum.
+__device__ __forceinline__ void run_pass(uint32_t smask, int nflag, int wave, int lane, int cC, int s0, int e_seg,
+                                      int e_row, int e_lo0, int e_lo1, uint32_t dm, const uint32_t* ring,
+                                      const int32_t (*tlo)[kGroups], const int32_t (*thi)[kGroups],
+                                      const double (*tden)[kGroups], RunSum* wsum, Emitter em, double theta) {
+  const int slot = 4 * wave + (lane >> 4);
+  const bool act = slot < nflag;
+  uint32_t mm = smask;
+  for (int k = 0; k < slot && mm; ++k) mm &= mm - 1u;
+  const int j = act ? __ffs(mm) - 1 : 0;
+  const int g = lane & 15;
+  const int w = 1 << j, sh = group_shift(w);
+  const int e0 = cC - sh + 64 * g;  // window end of the group's position 0
+  const int vhi = min(e_seg + w - 1, e_row);
+  const int vlo = max(w, max(e_lo0, e_lo1 + w));
+  const int pa = act ? max(0, vlo - e0) : 64, pb = min(63, vhi - e0);  // valid positions [pa, pb]
+  const int lo = tlo[j][g], hi = thi[j][g];
+  const double den = tden[j][g];
+  const int i0 = s0 + e0 - w;  // sample index of position 0
+  em.width = (uint32_t)w;
+  em.writer = act;
+  bool inrun = false, rhead = false, hflag = false;
+  int cS = 0, cp = 0, hS = 0, hp = 0;
+  auto visit = [&](int p, int S) {
+    const bool valid = p >= pa && p <= pb;
+    bool ab = valid && S >= hi && hi != INT_MAX;
+    if (valid && S > lo && !ab) ab = (double)S / den > theta;  // 3-integer band only
+    if (valid && !ab && inrun) {  // a run ends before p
+      if (rhead) {
+        hflag = true;
+        hS = cS;
+        hp = cp;
+      } else {
+        emit(em, i0 + cp, cS, den);
+      }
+    }
+    const bool newrun = ab && !inrun;
+    const bool upd = newrun || (ab && S > cS);
+    rhead = newrun ? p == pa : rhead;
+    cS = upd ? S : cS;
+    cp = upd ? p : cp;
+    inrun = valid ? ab : inrun;
+  };
+  if (w >= 8) {
+    // e0 and w are multiples of 4: four positions per LDS read
+    for (int p = 0; p < 64; p += 4) {
+      const uint4 a = *reinterpret_cast<const uint4*>(&ring[(e0 + p) & (kRing - 1)]);
+      const uint4 b = *reinterpret_cast<const uint4*>(&ring[(e0 + p - w) & (kRing - 1)]);
+      visit(p, (int)(a.x - b.x));
+      visit(p + 1, (int)(a.y - b.y));
+      visit(p + 2, (int)(a.z - b.z));
+      visit(p + 3, (int)(a.w - b.w));
+    }
+  } else {
+    for (int p = 0; p < 64; ++p)
+      visit(p, (int)(ring[(e0 + p) & (kRing - 1)] - ring[(e0 + p - w) & (kRing - 1)]));
+  }
+  RunSum gs = rs_empty();
+  if (pa <= pb) {
+    gs.flags = kNonEmpty;
+    if (inrun && rhead) {
+      gs.flags |= kFull | kHead;
+      gs.hi = i0 + cp; gs.hS = cS; gs.hd = den;
+    } else {
+      if (hflag) { gs.flags |= kHead; gs.hi = i0 + hp; gs.hS = hS; gs.hd = den; }
+      if (inrun) { gs.flags |= kTail; gs.ti = i0 + cp; gs.tS = cS; gs.td = den; }
+    }
+  }
+  gs = rs_absorb<1>(gs, g, act, em);
+  gs = rs_absorb<2>(gs, g, act, em);
+  gs = rs_absorb<4>(gs, g, act, em);
+  gs = rs_absorb<8>(gs, g, act, em);
+  if (act && g == 0) wsum[j] = gs;
 }
 
 // NW > 0: the number of widths is a compile-time constant (fast pass unrolled);
@@ -103,7 +166,7 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
   __shared__ int32_t thi[kMaxWidths][kGroups];
   __shared__ double tden[kMaxWidths][kGroups];
   __shared__ RunSum carry[kMaxWidths];
-  __shared__ RunSum wsum[kMaxWidths][4];
+  __shared__ RunSum wsum[kMaxWidths];
   __shared__ sps_cand cbuf[2][kCbuf];
   __shared__ uint32_t wtot[2][4];
   __shared__ uint32_t step_mask, flush_n, flush_base;
@@ -274,33 +337,10 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
         if (base + i < A.cap) A.cands[base + i] = cbuf[buf ^ 1][i];
     }
     const uint32_t smask = step_mask;
-    for (int j = 0; j < nw; ++j) {
-      if (!((smask >> j) & 1u)) continue;
-      const int w = 1 << j, sh = group_shift(w);
-      const int eg = cC - sh + 256 * wave;
-      const int vhi = min(e_seg + w - 1, e_row);
-      const int vlo = max(w, max(e_lo0, e_lo1 + w));
-      const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, lane == 0,
-                       A.sample_offset};
-      RunSum acc = rs_empty();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e0 = eg + 64 * q, g = 4 * wave + q;
-        const int e = e0 + lane;
-        const int S = (int)(ring[e & (kRing - 1)] - ring[(e - w) & (kRing - 1)]);
-        Bound bd;
-        bd.lo = readfirst(tlo[j][g]);
-        bd.hi = readfirst(thi[j][g]);
-        bd.den = tden[j][g];
-        const double d = bd.den;
-        const bool is_above = above(S, bd, A.theta);
-        const uint64_t V = lane_range(vlo - e0, vhi - e0);
-        const uint64_t M = ballot(is_above) & V;
-        const RunSum gs = group_summary(M, V, S, d, s0 + e0 - w, lane, em);
-        acc = rs_combine(acc, gs, em);
-      }
-      if (lane == 0) wsum[j][wave] = acc;
-    }
+    const int nflag = __popc(smask);
+    if (4 * wave < nflag) run_pass(smask, nflag, wave, lane, cC, s0, e_seg, e_row, e_lo0, e_lo1, dm, ring, tlo,
+                                   thi, tden, wsum, Emitter{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm,
+                                                           0u, false, A.sample_offset}, A.theta);
     cur_mad = next_mad;
     __syncthreads();  // BC
 
@@ -312,7 +352,7 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
       RunSum cj = carry[j];
       bool dirty = false;
       if ((smask >> j) & 1u) {
-        for (int v = 0; v < 4; ++v) cj = rs_combine(cj, wsum[j][v], em);
+        cj = rs_combine(cj, wsum[j], em);
         dirty = true;
       } else {
         // nothing above for width j: a non-empty step closes an open run

@@ -81,4 +81,20 @@ __device__ __forceinline__ uint64_t lane_range(int lo, int hi) {
   return (lo > hi || hi < 0 || lo > 63) ? 0ull : m;
 }
 
+// Value of lane i + D of the same row of 16 lanes (DPP row_shl:D); lanes
+// whose source lies past the row end receive `old`.
+template <int D>
+__device__ __forceinline__ int row_down(int old, int v) {
+  static_assert(D >= 1 && D <= 15, "row_shl range");
+  return dpp<0x100 + D>(old, v);
+}
+
+template <int D>
+__device__ __forceinline__ double row_down(double old, double v) {
+  const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+  const int lo = row_down<D>((int)(uint32_t)o, (int)(uint32_t)x);
+  const int hi = row_down<D>((int)(o >> 32), (int)(x >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (uint32_t)lo);
+}
+
 }  // namespace sps
