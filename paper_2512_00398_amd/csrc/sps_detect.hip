@@ -41,17 +41,51 @@ constexpr int kC = 1024;                 // samples (window ends) per step
 constexpr int kRing = 8192;              // ring entries, >= kC + 64 + max width
 constexpr int kGroups = kC / 64;         // 64-position groups per step and width
 
-// Window ends of width w in a step start (64 - ceil(w/2) mod 64) mod 64
-// before the step, so that every 64-lane group shares one centre block.
-__device__ __forceinline__ int group_shift(int w) {
-  const int sub = w - (w >> 1);
-  return (64 - (sub & 63)) & 63;
+// Best (largest S, earliest lane) of the lanes in `run`; wave-uniform result.
+__device__ __forceinline__ void run_best(uint64_t run, int S, int lane, int& bestS, int& bestLane) {
+  const bool in = (run >> lane) & 1ull;
+  bestS = wave_max_u(in ? S : INT_MIN);
+  bestLane = ctz(ballot(in && S == bestS));
+}
+
+// A 64-position group's run summary, packed for LDS: x = flags | head best
+// lane << 8 | tail best lane << 16, y = head S, z = tail S, w = MAD of the
+// group's centre block (the group's S/N denominator is K * MAD * sqrt(w)).
+// M: above lanes, V: valid lanes (contiguous). Runs touching neither end of
+// the valid lanes are emitted here; `full_best`/`full_lane` is the best of
+// all valid lanes (used when every valid lane is above).
+__device__ __forceinline__ uint4 group_pack(uint64_t M, uint64_t V, int S, int mad, double den, int i0, int lane,
+                                            int full_best, const Emitter& E) {
+  if (!V) return make_uint4(0u, 0u, 0u, (uint32_t)mad);
+  if (!M) return make_uint4((uint32_t)kNonEmpty, 0u, 0u, (uint32_t)mad);
+  if (M == V) {
+    const int bl = ctz(ballot(((V >> lane) & 1ull) && S == full_best));
+    return make_uint4((uint32_t)(kNonEmpty | kFull | kHead) | ((uint32_t)bl << 8), (uint32_t)full_best, 0u,
+                      (uint32_t)mad);
+  }
+  uint32_t flags = kNonEmpty;
+  int hl = 0, tl = 0, hS = 0, tS = 0;
+  const int fv = ctz(V), lv = msb(V);
+  uint64_t m = M;
+  while (m) {
+    const int a = ctz(m);
+    const uint64_t gap = ~m & (~0ull << a);
+    const int b = gap ? ctz(gap) : 64;
+    const uint64_t run = (b == 64 ? ~0ull : ((1ull << b) - 1ull)) & (~0ull << a);
+    int bs, bl;
+    run_best(run, S, lane, bs, bl);
+    if (a == fv) { flags |= kHead; hl = bl; hS = bs; }
+    else if (b - 1 == lv) { flags |= kTail; tl = bl; tS = bs; }
+    else emit(E, i0 + bl, bs, den);
+    m &= ~run;
+  }
+  return make_uint4(flags | ((uint32_t)hl << 8) | ((uint32_t)tl << 16), (uint32_t)hS, (uint32_t)tS, (uint32_t)mad);
 }
 
 // One level of the in-order combine of 16 group summaries held by the lanes
 // of a DPP row: lanes at multiples of 2D absorb the summary of lane + D.
 template <int D>
-__device__ __forceinline__ RunSum rs_absorb(const RunSum& g, int grp, bool act, const Emitter& em) {
+__device__ __forceinline__ RunSum rs_absorb(const RunSum& g, int k, bool act, const Emitter& em) {
   RunSum r;
   r.flags = row_down<D>(0, g.flags);
   r.hi = row_down<D>(0, g.hi);
@@ -61,91 +95,18 @@ __device__ __forceinline__ RunSum rs_absorb(const RunSum& g, int grp, bool act, 
   r.pad = 0;
   r.hd = row_down<D>(1.0, g.hd);
   r.td = row_down<D>(1.0, g.td);
-  const bool mine = (grp & (2 * D - 1)) == 0;
+  const bool mine = (k & (2 * D - 1)) == 0;
   Emitter e = em;
   e.writer = act && mine;
   const RunSum c = rs_combine(g, r, e);
   return mine ? c : g;
 }
 
-// Run pass of one step over its flagged widths. Lane (wave, l) takes group
-// l % 16 of the (4 * wave + l / 16)-th flagged width: the 64 window ends of
-// one centre block, scanned in order (so the group's best is the largest S,
-// earliest on ties), runs inside the group emitted at once. The 16 group
-// summaries of a width (one DPP row) are then combined in order; lane 0 of
-// the row leaves the step's summary of that width in wsum.
-__device__ __forceinline__ void run_pass(uint32_t smask, int nflag, int wave, int lane, int cC, int s0, int e_seg,
-                                      int e_row, int e_lo0, int e_lo1, uint32_t dm, const uint32_t* ring,
-                                      const int32_t (*tlo)[kGroups], const int32_t (*thi)[kGroups],
-                                      const double (*tden)[kGroups], RunSum* wsum, Emitter em, double theta) {
-  const int slot = 4 * wave + (lane >> 4);
-  const bool act = slot < nflag;
-  uint32_t mm = smask;
-  for (int k = 0; k < slot && mm; ++k) mm &= mm - 1u;
-  const int j = act ? __ffs(mm) - 1 : 0;
-  const int g = lane & 15;
-  const int w = 1 << j, sh = group_shift(w);
-  const int e0 = cC - sh + 64 * g;  // window end of the group's position 0
-  const int vhi = min(e_seg + w - 1, e_row);
-  const int vlo = max(w, max(e_lo0, e_lo1 + w));
-  const int pa = act ? max(0, vlo - e0) : 64, pb = min(63, vhi - e0);  // valid positions [pa, pb]
-  const int lo = tlo[j][g], hi = thi[j][g];
-  const double den = tden[j][g];
-  const int i0 = s0 + e0 - w;  // sample index of position 0
-  em.width = (uint32_t)w;
-  em.writer = act;
-  bool inrun = false, rhead = false, hflag = false;
-  int cS = 0, cp = 0, hS = 0, hp = 0;
-  auto visit = [&](int p, int S) {
-    const bool valid = p >= pa && p <= pb;
-    bool ab = valid && S >= hi && hi != INT_MAX;
-    if (valid && S > lo && !ab) ab = (double)S / den > theta;  // 3-integer band only
-    if (valid && !ab && inrun) {  // a run ends before p
-      if (rhead) {
-        hflag = true;
-        hS = cS;
-        hp = cp;
-      } else {
-        emit(em, i0 + cp, cS, den);
-      }
-    }
-    const bool newrun = ab && !inrun;
-    const bool upd = newrun || (ab && S > cS);
-    rhead = newrun ? p == pa : rhead;
-    cS = upd ? S : cS;
-    cp = upd ? p : cp;
-    inrun = valid ? ab : inrun;
-  };
-  if (w >= 8) {
-    // e0 and w are multiples of 4: four positions per LDS read
-    for (int p = 0; p < 64; p += 4) {
-      const uint4 a = *reinterpret_cast<const uint4*>(&ring[(e0 + p) & (kRing - 1)]);
-      const uint4 b = *reinterpret_cast<const uint4*>(&ring[(e0 + p - w) & (kRing - 1)]);
-      visit(p, (int)(a.x - b.x));
-      visit(p + 1, (int)(a.y - b.y));
-      visit(p + 2, (int)(a.z - b.z));
-      visit(p + 3, (int)(a.w - b.w));
-    }
-  } else {
-    for (int p = 0; p < 64; ++p)
-      visit(p, (int)(ring[(e0 + p) & (kRing - 1)] - ring[(e0 + p - w) & (kRing - 1)]));
-  }
-  RunSum gs = rs_empty();
-  if (pa <= pb) {
-    gs.flags = kNonEmpty;
-    if (inrun && rhead) {
-      gs.flags |= kFull | kHead;
-      gs.hi = i0 + cp; gs.hS = cS; gs.hd = den;
-    } else {
-      if (hflag) { gs.flags |= kHead; gs.hi = i0 + hp; gs.hS = hS; gs.hd = den; }
-      if (inrun) { gs.flags |= kTail; gs.ti = i0 + cp; gs.tS = cS; gs.td = den; }
-    }
-  }
-  gs = rs_absorb<1>(gs, g, act, em);
-  gs = rs_absorb<2>(gs, g, act, em);
-  gs = rs_absorb<4>(gs, g, act, em);
-  gs = rs_absorb<8>(gs, g, act, em);
-  if (act && g == 0) wsum[j] = gs;
+// Window ends of width w in a step start (64 - ceil(w/2) mod 64) mod 64
+// before the step, so that every 64-lane group shares one centre block.
+__device__ __forceinline__ int group_shift(int w) {
+  const int sub = w - (w >> 1);
+  return (64 - (sub & 63)) & 63;
 }
 
 // NW > 0: the number of widths is a compile-time constant (fast pass unrolled);
@@ -155,8 +116,10 @@ __device__ __forceinline__ void run_pass(uint32_t smask, int nflag, int wave, in
 //   A  write P of step c into the ring; bounds for step c's centre blocks
 //   B  fast pass over step c; residuals and wave scan of step c+1; flush slot
 //      for the candidates staged during step c-1
-//   C  copy those candidates out; run pass over step c's flagged widths
-//   D  (no barrier) owner waves fold step c into their widths' summaries
+//   C  copy those candidates out; run pass over step c's flagged widths:
+//      one packed summary per (width, 64-position group) into LDS
+//   D  DPP row trees combine each flagged width's 16 group summaries and
+//      fold them into the width's carried run (no barrier before the next A)
 // Samples, medians and MADs are fetched one step ahead of their use.
 template <int NW, bool VIRT>
 __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task) {
@@ -164,9 +127,9 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
   __shared__ uint32_t ring[kRing];
   __shared__ int32_t tlo[kMaxWidths][kGroups];
   __shared__ int32_t thi[kMaxWidths][kGroups];
-  __shared__ double tden[kMaxWidths][kGroups];
+  __shared__ int32_t tmad[kMaxWidths][kGroups];
+  __shared__ uint4 gsum[kMaxWidths][kGroups];
   __shared__ RunSum carry[kMaxWidths];
-  __shared__ RunSum wsum[kMaxWidths];
   __shared__ sps_cand cbuf[2][kCbuf];
   __shared__ uint32_t wtot[2][4];
   __shared__ uint32_t step_mask, flush_n, flush_base;
@@ -266,7 +229,7 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
       const Bound bd = make_bound(cur_mad, tsq, A.theta);
       tlo[tj][tg] = bd.lo;
       thi[tj][tg] = bd.hi;
-      tden[tj][tg] = bd.den;
+      tmad[tj][tg] = cur_mad;
     }
     if (c + 1 < nsteps) next_mad = fetch_mad(c + 1);
     if (tid == 0) step_mask = 0u;
@@ -337,40 +300,107 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
         if (base + i < A.cap) A.cands[base + i] = cbuf[buf ^ 1][i];
     }
     const uint32_t smask = step_mask;
-    const int nflag = __popc(smask);
-    if (4 * wave < nflag) run_pass(smask, nflag, wave, lane, cC, s0, e_seg, e_row, e_lo0, e_lo1, dm, ring, tlo,
-                                   thi, tden, wsum, Emitter{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm,
-                                                           0u, false, A.sample_offset}, A.theta);
+    for (int j = 0; j < nw; ++j) {
+      if (!((smask >> j) & 1u)) continue;
+      const int w = 1 << j, sh = group_shift(w);
+      const int eg = cC - sh + 256 * wave;
+      const int vhi = min(e_seg + w - 1, e_row);
+      const int vlo = max(w, max(e_lo0, e_lo1 + w));
+      const double sqw = A.sqrtw[j];
+      const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, lane == 0,
+                       A.sample_offset};
+      const int4 LO = *reinterpret_cast<const int4*>(&tlo[j][4 * wave]);
+      const int4 HI = *reinterpret_cast<const int4*>(&thi[j][4 * wave]);
+      const int4 MD = *reinterpret_cast<const int4*>(&tmad[j][4 * wave]);
+      int S[4], best[4];
+      uint64_t M[4], V[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = eg + 64 * q + lane;
+        S[q] = (int)(ring[e & (kRing - 1)] - ring[(e - w) & (kRing - 1)]);
+        const int lo = q == 0 ? LO.x : q == 1 ? LO.y : q == 2 ? LO.z : LO.w;
+        const int hi = q == 0 ? HI.x : q == 1 ? HI.y : q == 2 ? HI.z : HI.w;
+        const int mad = q == 0 ? MD.x : q == 1 ? MD.y : q == 2 ? MD.z : MD.w;
+        bool ab = S[q] >= hi && hi != INT_MAX;
+        if (S[q] > lo && !ab) ab = (double)S[q] / ((kMadToSigma * (double)mad) * sqw) > A.theta;
+        V[q] = lane_range(vlo - eg - 64 * q, vhi - eg - 64 * q);
+        const bool in = ab && ((V[q] >> lane) & 1ull);
+        M[q] = ballot(in);
+        best[q] = wave_max_u(in ? S[q] : INT_MIN);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int mad = q == 0 ? MD.x : q == 1 ? MD.y : q == 2 ? MD.z : MD.w;
+        const uint4 pk = group_pack(M[q], V[q], S[q], mad, (kMadToSigma * (double)mad) * sqw,
+                                    s0 + eg + 64 * q - w, lane, best[q], em);
+        if (lane == 0) gsum[j][4 * wave + q] = pk;
+      }
+    }
     cur_mad = next_mad;
     __syncthreads();  // BC
 
-    // ---- D: width j is owned by wave j % 4
+    // ---- D: the 16 group summaries of each flagged width are combined in
+    // order by a DPP row tree (one row of 16 lanes per width, four widths per
+    // wave; the wave that takes the first four rotates with the step), then
+    // folded into the width's carried run. Unflagged widths only close a run.
+    {
+      const int nflag = __popc(smask);
+      const int r = lane >> 4, k = lane & 15;
+      const int slot = 4 * ((wave + c) & 3) + r;
+      if (4 * ((wave + c) & 3) < nflag) {
+        const bool act = slot < nflag;
+        uint32_t mm = smask;
+        for (int t = 0; t < slot && mm; ++t) mm &= mm - 1u;
+        const int j = act ? __ffs(mm) - 1 : 0;
+        const int w = 1 << j, sh = group_shift(w);
+        const uint4 pk = gsum[j][k];
+        RunSum gs = rs_empty();
+        if (act) {
+          const double den = (kMadToSigma * (double)(int)pk.w) * A.sqrtw[j];
+          const int i0 = s0 + cC - sh + 64 * k - w;
+          gs.flags = (int)(pk.x & 15u);
+          gs.hi = i0 + (int)((pk.x >> 8) & 63u);
+          gs.ti = i0 + (int)((pk.x >> 16) & 63u);
+          gs.hS = (int)pk.y;
+          gs.tS = (int)pk.z;
+          gs.hd = den;
+          gs.td = den;
+        }
+        const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, false,
+                         A.sample_offset};
+        gs = rs_absorb<1>(gs, k, act, em);
+        gs = rs_absorb<2>(gs, k, act, em);
+        gs = rs_absorb<4>(gs, k, act, em);
+        gs = rs_absorb<8>(gs, k, act, em);
+        if (act && k == 0) {
+          Emitter e0 = em;
+          e0.writer = true;
+          carry[j] = rs_combine(carry[j], gs, e0);
+        }
+      }
+    }
     for (int j = wave; j < nw; j += 4) {
+      if ((smask >> j) & 1u) continue;
       const int w = 1 << j, sh = group_shift(w);
       const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, lane == 0,
                        A.sample_offset};
       RunSum cj = carry[j];
-      bool dirty = false;
-      if ((smask >> j) & 1u) {
-        cj = rs_combine(cj, wsum[j], em);
-        dirty = true;
-      } else {
-        // nothing above for width j: a non-empty step closes an open run
-        const int elo = max(cC - sh, max(w, max(e_lo0, e_lo1 + w)));
-        const int ehi = min(cC - sh + kC - 1, min(e_seg + w - 1, e_row));
-        if (elo <= ehi) {
-          if (!(cj.flags & kNonEmpty)) {
-            cj.flags = kNonEmpty;
-            dirty = true;
-          } else if (cj.flags & (kTail | kFull)) {
-            RunSum below = rs_empty();
-            below.flags = kNonEmpty;
-            cj = rs_combine(cj, below, em);
-            dirty = true;
-          }
+      // nothing above for width j: a non-empty step closes an open run
+      const int elo = max(cC - sh, max(w, max(e_lo0, e_lo1 + w)));
+      const int ehi = min(cC - sh + kC - 1, min(e_seg + w - 1, e_row));
+      if (elo <= ehi) {
+        bool dirty = false;
+        if (!(cj.flags & kNonEmpty)) {
+          cj.flags = kNonEmpty;
+          dirty = true;
+        } else if (cj.flags & (kTail | kFull)) {
+          RunSum below = rs_empty();
+          below.flags = kNonEmpty;
+          cj = rs_combine(cj, below, em);
+          dirty = true;
         }
+        if (dirty && lane == 0) carry[j] = cj;
       }
-      if (dirty && lane == 0) carry[j] = cj;
     }
   }
 

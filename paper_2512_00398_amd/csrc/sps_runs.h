@@ -10,7 +10,7 @@
 namespace sps {
 namespace {
 
-constexpr int kCbuf = 64;  // LDS candidate staging records per buffer
+constexpr int kCbuf = 48;  // LDS candidate staging records per buffer
 
 // The S/N test of one (centre block, width): den = (K * MAD) * sqrt(w);
 // "S / den > theta" holds for S >= hi (when hi < INT_MAX), fails for

@@ -218,6 +218,48 @@ __device__ __forceinline__ bool fast_query(Chain<NB, VIRT>& c) {
   return true;
 }
 
+// Narrow local query (the common case): 16 bins around each of the three
+// pivots, one DPP row (16 lanes) per pivot, one row-local prefix sum for all
+// three. Row 0 finds the new median within [m - 8, m + 7]; row 3 lanes test
+// MAD candidates d + t around it from rows 1 (lower pivot) and 2 (upper
+// pivot). Returns false when the answer may lie outside these windows.
+template <int NB, bool VIRT>
+__device__ __forceinline__ bool narrow_query(Chain<NB, VIRT>& c) {
+  const int rho = (c.n - 1) >> 1;
+  const int im = c.m - c.base, iL = c.m - c.d - c.base, iU = c.m + c.d + 1 - c.base;
+  if (iL - 8 < 0 || iU + 8 > NB) return false;  // im lies between them
+  const int lane = c.lane, r = lane >> 4, k = lane & 15;
+  const int ib = r == 0 ? im : (r == 1 ? iL : iU);
+  const int h = hist_get(c.H, ib - 8 + k);
+  const int inc = row_scan_incl(h);
+  const int i0 = readlane(inc, 7), i1 = readlane(inc, 23), i2 = readlane(inc, 39);
+  const int cb = r == 0 ? c.cm - i0 : (r == 1 ? c.cL - i1 : c.cU - i2);
+  const int lt = cb + inc - h;  // #{x < pivot - 8 + k} in rows 0..2
+  const uint64_t mk = ballot(lt + h > rho) & 0xFFFFull;
+  if (!mk) return false;       // median above the window
+  const int j = ctz(mk);
+  const int ltj = readlane(lt, j);
+  if (ltj > rho) return false;  // median below the window
+  const int delta = j - 8;
+  // row 3: lane tests d' = d + t, t = k - 8, around m' = m + delta:
+  // #{|x - m'| <= d'} = #{x < pU + delta + t} - #{x < pL + delta - t}
+  const int t = k - 8;
+  const int kl = 8 + delta - t, ku = 8 + delta + t;
+  const bool ok = r == 3 && kl >= 0 && kl < 16 && ku >= 0 && ku < 16 && c.d + t >= 0;
+  const int va = __shfl(lt, 16 + (kl & 15), 64), vb = __shfl(lt, 32 + (ku & 15), 64);
+  const uint64_t okm = ballot(ok), fm = ballot(ok && vb - va > rho);
+  if (!fm) return false;        // MAD above the tested range
+  const int jj = ctz(fm);
+  const int dp = c.d + readlane(t, jj);
+  if (jj == ctz(okm) && dp > 0) return false;  // MAD may be smaller still
+  c.m = c.m + delta;
+  c.cm = ltj;
+  c.d = dp;
+  c.cL = readlane(va, jj);
+  c.cU = readlane(vb, jj);
+  return true;
+}
+
 // Exact answer for window [lo, hi) from the samples themselves, then a
 // histogram centred on the median when the data allow one.
 template <int NB, bool VIRT>
@@ -286,7 +328,7 @@ __device__ __forceinline__ void chain_step(Chain<NB, VIRT>& c, int lo, int hi, b
   c.cL += popc(ballot(a_ok && av < pL)) - popc(ballot(b_ok && bv < pL));
   c.cU += popc(ballot(a_ok && av < pU)) - popc(ballot(b_ok && bv < pU));
   wave_lds_fence();
-  if (!fast_query(c)) slow_block(c, lo, hi);
+  if (!narrow_query(c) && !fast_query(c)) slow_block(c, lo, hi);
 }
 
 // WPG chains (waves) per workgroup; LDS = WPG * NB * 2 bytes. Blocks

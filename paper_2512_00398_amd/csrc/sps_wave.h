@@ -81,6 +81,15 @@ __device__ __forceinline__ uint64_t lane_range(int lo, int hi) {
   return (lo > hi || hi < 0 || lo > 63) ? 0ull : m;
 }
 
+// Inclusive prefix sum within each row of 16 lanes.
+__device__ __forceinline__ int row_scan_incl(int v) {
+  v += dpp<0x111>(0, v);
+  v += dpp<0x112>(0, v);
+  v += dpp<0x114>(0, v);
+  v += dpp<0x118>(0, v);
+  return v;
+}
+
 // Value of lane i + D of the same row of 16 lanes (DPP row_shl:D); lanes
 // whose source lies past the row end receive `old`.
 template <int D>
