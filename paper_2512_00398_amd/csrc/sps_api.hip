@@ -494,7 +494,7 @@ struct StreamHeader {
   int32_t tmin;
   int32_t pad;
 };
-constexpr uint64_t kStreamMagic = 0x5350535354524D31ull;  // "SPSSTRM1"
+constexpr uint64_t kStreamMagic = 0x5350535354524D32ull;  // "SPSSTRM2"
 
 // History length, virtual row and detection segments of a stream on plan p.
 bool stream_geometry(const sps_plan* p, sps_stream* s) {

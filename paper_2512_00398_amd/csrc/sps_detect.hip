@@ -8,11 +8,9 @@
 // test "S / den > theta", den = (K * MAD_{k*}) * sqrt(w), is decided by
 // integer bounds lo < S < hi per (centre block, width) and, inside that
 // 3-integer band only, by the IEEE double division itself. Within one centre
-// block S/N is strictly increasing in S, so run maxima are found on S; best
-// positions are compared across blocks by cross-multiplication and only a
-// near-tie falls back to the two divisions, which reproduces the comparison of
-// the rounded S/N values exactly. The S/N value itself is divided once, when a
-// candidate is emitted.
+// block S/N is strictly increasing in S, so the best of a run inside a group
+// is found on S; each group best is then divided once, and bests are compared
+// across groups, steps and segments on those exact double S/N values.
 //
 // Layout (gfx950, wave64). One 256-thread workgroup streams one segment of a
 // row in steps of 1024 samples: coalesced float4 loads, residuals, a
@@ -21,10 +19,10 @@
 // group shares one centre block k* (window ends E with E - ceil(w/2) = 0 mod
 // 64): the group's bound is one scalar. Fast pass: per lane and width two LDS
 // reads, a subtract and a compare folded into a ballot. Widths with any
-// position beyond the bound take the run pass: the above-mask of each group
-// is walked in scalar code, a DPP max-reduction finds each run's best S, and
-// associative RunSum summaries stitch runs across groups, waves (one owner
-// wave per width), steps and, through the fix-up kernel, segments.
+// position beyond the bound take the run pass: per group a DPP max-reduction
+// and a packed summary in LDS, then DPP row trees over the 16 groups of each
+// flagged width, folded into the carried run summaries that stitch runs
+// across steps and, through the fix-up kernel, segments.
 // Candidates are staged in LDS and flushed with one global atomic per step.
 #include <climits>
 #include <type_traits>
@@ -76,7 +74,7 @@ __device__ __forceinline__ uint4 group_pack(uint64_t M, uint64_t V, int S, int m
     run_best(run, S, lane, bs, bl);
     if (a == fv) { flags |= kHead; hl = bl; hS = bs; }
     else if (b - 1 == lv) { flags |= kTail; tl = bl; tS = bs; }
-    else emit(E, i0 + bl, bs, den);
+    else emit(E, i0 + bl, (double)bs / den);
     m &= ~run;
   }
   return make_uint4(flags | ((uint32_t)hl << 8) | ((uint32_t)tl << 16), (uint32_t)hS, (uint32_t)tS, (uint32_t)mad);
@@ -90,11 +88,9 @@ __device__ __forceinline__ RunSum rs_absorb(const RunSum& g, int k, bool act, co
   r.flags = row_down<D>(0, g.flags);
   r.hi = row_down<D>(0, g.hi);
   r.ti = row_down<D>(0, g.ti);
-  r.hS = row_down<D>(0, g.hS);
-  r.tS = row_down<D>(0, g.tS);
   r.pad = 0;
-  r.hd = row_down<D>(1.0, g.hd);
-  r.td = row_down<D>(1.0, g.td);
+  r.hq = row_down<D>(0.0, g.hq);
+  r.tq = row_down<D>(0.0, g.tq);
   const bool mine = (k & (2 * D - 1)) == 0;
   Emitter e = em;
   e.writer = act && mine;
@@ -361,10 +357,8 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
           gs.flags = (int)(pk.x & 15u);
           gs.hi = i0 + (int)((pk.x >> 8) & 63u);
           gs.ti = i0 + (int)((pk.x >> 16) & 63u);
-          gs.hS = (int)pk.y;
-          gs.tS = (int)pk.z;
-          gs.hd = den;
-          gs.td = den;
+          gs.hq = (double)(int)pk.y / den;
+          gs.tq = (double)(int)pk.z / den;
         }
         const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, false,
                          A.sample_offset};
@@ -505,7 +499,7 @@ __global__ __launch_bounds__(256) void k_stream_fold(StreamArgs A) {
   const RunSum* f = A.frag + (int64_t)t * A.nseg;
   for (int s = 0; s < A.nseg; ++s) acc = rs_combine(acc, rs_shift(f[s], -A.Hx), em);
   if ((acc.flags & kHead) && !(acc.flags & kFull)) {
-    emit(em, acc.hi, acc.hS, acc.hd);
+    emit(em, acc.hi, acc.hq);
     acc.flags &= ~kHead;
   }
   A.carry[t] = rs_shift(acc, -A.ngulp);

@@ -20,18 +20,17 @@ constexpr double kMadToSigma = 1.482602218505602;
 // position (if above and the range is not entirely above); full: every
 // position above (then head holds the best of the whole range). Runs touching
 // neither end were already emitted when the summary was formed. A best
-// position is kept as (sample, S, den): its S/N is S / den in IEEE double.
+// position is kept as (sample, S/N) with the S/N the IEEE double S / den, so
+// bests compare exactly as the definition orders them.
 struct RunSum {
   int32_t flags;  // bit0 nonempty, bit1 full, bit2 head valid, bit3 tail valid
   int32_t hi;     // sample index of the head run's best position
   int32_t ti;     // sample index of the tail run's best position
-  int32_t hS;     // boxcar sum at hi
-  int32_t tS;     // boxcar sum at ti
   int32_t pad;
-  double hd;      // S/N denominator (K * MAD) * sqrt(w) at hi
-  double td;      // ... at ti
+  double hq;      // S/N at hi
+  double tq;      // S/N at ti
 };
-static_assert(sizeof(RunSum) == 40, "RunSum layout");
+static_assert(sizeof(RunSum) == 32, "RunSum layout");
 
 enum : int32_t { kNonEmpty = 1, kFull = 2, kHead = 4, kTail = 8 };
 

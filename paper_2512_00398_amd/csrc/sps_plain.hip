@@ -119,12 +119,11 @@ __global__ __launch_bounds__(256) void k_plain_peaks(PlainArgs A) {
         const bool in = (run >> lane) & 1ull;
         const double km = wave_max_f64(in ? key : -1.0);
         const int j = ctz(ballot(in && key == km));
-        const int bS = readlane(S, j);
-        const double bd = __shfl(d, j, 64);
-        if (a0 == fv && b0 - 1 == lv) { gs.flags |= kFull | kHead; gs.hi = g + j; gs.hS = bS; gs.hd = bd; }
-        else if (a0 == fv) { gs.flags |= kHead; gs.hi = g + j; gs.hS = bS; gs.hd = bd; }
-        else if (b0 - 1 == lv) { gs.flags |= kTail; gs.ti = g + j; gs.tS = bS; gs.td = bd; }
-        else emit(em, g + j, bS, bd);
+        const double bq = km;  // the run's best S/N, S / den at lane j
+        if (a0 == fv && b0 - 1 == lv) { gs.flags |= kFull | kHead; gs.hi = g + j; gs.hq = bq; }
+        else if (a0 == fv) { gs.flags |= kHead; gs.hi = g + j; gs.hq = bq; }
+        else if (b0 - 1 == lv) { gs.flags |= kTail; gs.ti = g + j; gs.tq = bq; }
+        else emit(em, g + j, bq);
         m &= ~run;
       }
     }

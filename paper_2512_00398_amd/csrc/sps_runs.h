@@ -55,13 +55,13 @@ struct Emitter {
   int32_t soff;         // emitted sample = position - soff
 };
 
-__device__ __forceinline__ void emit(const Emitter& E, int32_t sample, int32_t S, double den) {
+__device__ __forceinline__ void emit(const Emitter& E, int32_t sample, double q) {
   if (!E.writer) return;
   sps_cand c;
   c.sample = sample - E.soff;
   c.dm_idx = E.dm;
   c.width = E.width;
-  c.snr = (float)((double)S / den);
+  c.snr = (float)q;
   if (E.cbuf) {
     const uint32_t s = atomicAdd(E.cbuf_n, 1u);
     if (s < (uint32_t)kCbuf) {
@@ -75,62 +75,47 @@ __device__ __forceinline__ void emit(const Emitter& E, int32_t sample, int32_t S
 
 __device__ __forceinline__ RunSum rs_empty() {
   RunSum r;
-  r.flags = 0; r.hi = 0; r.ti = 0; r.hS = 0; r.tS = 0; r.pad = 0; r.hd = 1.0; r.td = 1.0;
+  r.flags = 0; r.hi = 0; r.ti = 0; r.pad = 0; r.hq = 0.0; r.tq = 0.0;
   return r;
 }
 
-// true if S1/d1 at i1 beats S2/d2 at i2 in the rounded-double order (larger
-// S/N, earlier sample on ties). S > 0 and d > 0 for every above position.
-__device__ __forceinline__ bool beats(int S1, double d1, int i1, int S2, double d2, int i2) {
-  if (d1 == d2) return S1 > S2 || (S1 == S2 && i1 < i2);
-  const double a = (double)S1 * d2, b = (double)S2 * d1;
-  // a, b carry < 2^-53 relative error each: a gap of 1e-15 proves the
-  // rounded quotients differ in the same direction
-  if (a > b * (1.0 + 1e-15)) return true;
-  if (a < b * (1.0 - 1e-15)) return false;
-  const double q1 = (double)S1 / d1, q2 = (double)S2 / d2;
+// true if the best (q1 at i1) beats (q2 at i2): larger S/N, earlier on ties.
+__device__ __forceinline__ bool beats(double q1, int i1, double q2, int i2) {
   return q1 > q2 || (q1 == q2 && i1 < i2);
 }
 
-// Summary of range L followed immediately by range R. Runs that end at the
-// junction (and so touch neither end of L+R) are emitted.
-__device__ RunSum rs_combine(const RunSum& L, const RunSum& R, const Emitter& E) {
-  if (!(L.flags & kNonEmpty)) return R;
-  if (!(R.flags & kNonEmpty)) return L;
-  RunSum o = rs_empty();
-  o.flags = kNonEmpty;
-  if (L.flags & kFull) {
-    o.flags |= kHead;
-    o.hi = L.hi; o.hS = L.hS; o.hd = L.hd;
-    if ((R.flags & kHead) && beats(R.hS, R.hd, R.hi, o.hS, o.hd, o.hi)) { o.hi = R.hi; o.hS = R.hS; o.hd = R.hd; }
-    if (R.flags & kFull) { o.flags |= kFull; return o; }
-    if (R.flags & kTail) { o.flags |= kTail; o.ti = R.ti; o.tS = R.tS; o.td = R.td; }
-    return o;
-  }
-  if (L.flags & kHead) { o.flags |= kHead; o.hi = L.hi; o.hS = L.hS; o.hd = L.hd; }
-  if (R.flags & kFull) {
-    o.flags |= kTail;
-    o.ti = R.hi; o.tS = R.hS; o.td = R.hd;
-    if ((L.flags & kTail) && !beats(R.hS, R.hd, R.hi, L.tS, L.td, L.ti)) { o.ti = L.ti; o.tS = L.tS; o.td = L.td; }
-    return o;
-  }
-  if (R.flags & kTail) { o.flags |= kTail; o.ti = R.ti; o.tS = R.tS; o.td = R.td; }
-  const bool lt = L.flags & kTail, rh = R.flags & kHead;
-  if (lt && rh) {
-    if (beats(R.hS, R.hd, R.hi, L.tS, L.td, L.ti)) emit(E, R.hi, R.hS, R.hd);
-    else emit(E, L.ti, L.tS, L.td);
-  } else if (lt) {
-    emit(E, L.ti, L.tS, L.td);
-  } else if (rh) {
-    emit(E, R.hi, R.hS, R.hd);
-  }
-  return o;
+// Summary of range L followed immediately by range R. The run that ends at
+// the junction (touching neither end of L+R) is emitted. Written with
+// selects, so lanes holding different summaries combine without branching.
+__device__ __forceinline__ RunSum rs_combine(const RunSum& L, const RunSum& R, const Emitter& E) {
+  const bool Lne = L.flags & kNonEmpty, Rne = R.flags & kNonEmpty;
+  const bool Lf = L.flags & kFull, Lh = L.flags & kHead, Lt = L.flags & kTail;
+  const bool Rf = R.flags & kFull, Rh = R.flags & kHead, Rt = R.flags & kTail;
+  RunSum o;
+  o.pad = 0;
+  // head: L's head run, extended through R's head run when L is full
+  const bool hR = Lf && Rh && beats(R.hq, R.hi, L.hq, L.hi);
+  o.hi = hR ? R.hi : L.hi;
+  o.hq = hR ? R.hq : L.hq;
+  // tail: through R when R is full (joined with L's tail), else R's tail
+  const bool joinR = !Lf && Rf;
+  const bool keepL = joinR && Lt && !beats(R.hq, R.hi, L.tq, L.ti);
+  o.ti = keepL ? L.ti : (joinR ? R.hi : R.ti);
+  o.tq = keepL ? L.tq : (joinR ? R.hq : R.tq);
+  o.flags = kNonEmpty | ((Lf || Lh) ? kHead : 0) | ((Lf && Rf) ? kFull : 0) | ((joinR || (!Rf && Rt)) ? kTail : 0);
+  // the run ending at the junction
+  const bool junction = Lne && Rne && !Lf && !Rf && (Lt || Rh);
+  const bool pickR = Rh && (!Lt || beats(R.hq, R.hi, L.tq, L.ti));
+  const int ei = pickR ? R.hi : L.ti;
+  const double eq = pickR ? R.hq : L.tq;
+  if (junction) emit(E, ei, eq);
+  return !Lne ? R : (!Rne ? L : o);
 }
 
 // Runs touching the ends of a whole row are closed there.
 __device__ void rs_close(const RunSum& s, const Emitter& E) {
-  if (s.flags & kHead) emit(E, s.hi, s.hS, s.hd);
-  if (s.flags & kTail) emit(E, s.ti, s.tS, s.td);
+  if (s.flags & kHead) emit(E, s.hi, s.hq);
+  if (s.flags & kTail) emit(E, s.ti, s.tq);
 }
 
 }  // namespace
