@@ -95,7 +95,14 @@ __device__ __forceinline__ RunSum rs_absorb(const RunSum& g, int k, bool act, co
   Emitter e = em;
   e.writer = act && mine;
   const RunSum c = rs_combine(g, r, e);
-  return mine ? c : g;
+  RunSum o;
+  o.flags = mine ? c.flags : g.flags;
+  o.hi = mine ? c.hi : g.hi;
+  o.ti = mine ? c.ti : g.ti;
+  o.pad = 0;
+  o.hq = mine ? c.hq : g.hq;
+  o.tq = mine ? c.tq : g.tq;
+  return o;
 }
 
 // Window ends of width w in a step start (64 - ceil(w/2) mod 64) mod 64

@@ -86,30 +86,44 @@ __device__ __forceinline__ bool beats(double q1, int i1, double q2, int i2) {
 
 // Summary of range L followed immediately by range R. The run that ends at
 // the junction (touching neither end of L+R) is emitted. Written with
-// selects, so lanes holding different summaries combine without branching.
-__device__ __forceinline__ RunSum rs_combine(const RunSum& L, const RunSum& R, const Emitter& E) {
-  const bool Lne = L.flags & kNonEmpty, Rne = R.flags & kNonEmpty;
-  const bool Lf = L.flags & kFull, Lh = L.flags & kHead, Lt = L.flags & kTail;
-  const bool Rf = R.flags & kFull, Rh = R.flags & kHead, Rt = R.flags & kTail;
-  RunSum o;
-  o.pad = 0;
+// selects on scalars (never on whole summaries, which would make the
+// compiler select addresses and keep the summaries in scratch memory), so
+// lanes holding different summaries combine without branching.
+__device__ __forceinline__ RunSum rs_combine(const RunSum L, const RunSum R, const Emitter& E) {
+  const int Lfl = L.flags, Rfl = R.flags;
+  const int Lhi = L.hi, Lti = L.ti, Rhi = R.hi, Rti = R.ti;
+  const double Lhq = L.hq, Ltq = L.tq, Rhq = R.hq, Rtq = R.tq;
+  const bool Lne = Lfl & kNonEmpty, Rne = Rfl & kNonEmpty;
+  const bool Lf = Lfl & kFull, Lh = Lfl & kHead, Lt = Lfl & kTail;
+  const bool Rf = Rfl & kFull, Rh = Rfl & kHead, Rt = Rfl & kTail;
   // head: L's head run, extended through R's head run when L is full
-  const bool hR = Lf && Rh && beats(R.hq, R.hi, L.hq, L.hi);
-  o.hi = hR ? R.hi : L.hi;
-  o.hq = hR ? R.hq : L.hq;
+  const bool hR = Lf && Rh && beats(Rhq, Rhi, Lhq, Lhi);
+  int hi = hR ? Rhi : Lhi;
+  double hq = hR ? Rhq : Lhq;
   // tail: through R when R is full (joined with L's tail), else R's tail
   const bool joinR = !Lf && Rf;
-  const bool keepL = joinR && Lt && !beats(R.hq, R.hi, L.tq, L.ti);
-  o.ti = keepL ? L.ti : (joinR ? R.hi : R.ti);
-  o.tq = keepL ? L.tq : (joinR ? R.hq : R.tq);
-  o.flags = kNonEmpty | ((Lf || Lh) ? kHead : 0) | ((Lf && Rf) ? kFull : 0) | ((joinR || (!Rf && Rt)) ? kTail : 0);
+  const bool keepL = joinR && Lt && !beats(Rhq, Rhi, Ltq, Lti);
+  int ti = keepL ? Lti : (joinR ? Rhi : Rti);
+  double tq = keepL ? Ltq : (joinR ? Rhq : Rtq);
+  int fl = kNonEmpty | ((Lf || Lh) ? kHead : 0) | ((Lf && Rf) ? kFull : 0) | ((joinR || (!Rf && Rt)) ? kTail : 0);
   // the run ending at the junction
   const bool junction = Lne && Rne && !Lf && !Rf && (Lt || Rh);
-  const bool pickR = Rh && (!Lt || beats(R.hq, R.hi, L.tq, L.ti));
-  const int ei = pickR ? R.hi : L.ti;
-  const double eq = pickR ? R.hq : L.tq;
-  if (junction) emit(E, ei, eq);
-  return !Lne ? R : (!Rne ? L : o);
+  const bool pickR = Rh && (!Lt || beats(Rhq, Rhi, Ltq, Lti));
+  if (junction) emit(E, pickR ? Rhi : Lti, pickR ? Rhq : Ltq);
+  // an empty side leaves the other unchanged
+  fl = !Lne ? Rfl : (!Rne ? Lfl : fl);
+  hi = !Lne ? Rhi : (!Rne ? Lhi : hi);
+  ti = !Lne ? Rti : (!Rne ? Lti : ti);
+  hq = !Lne ? Rhq : (!Rne ? Lhq : hq);
+  tq = !Lne ? Rtq : (!Rne ? Ltq : tq);
+  RunSum o;
+  o.flags = fl;
+  o.hi = hi;
+  o.ti = ti;
+  o.pad = 0;
+  o.hq = hq;
+  o.tq = tq;
+  return o;
 }
 
 // Runs touching the ends of a whole row are closed there.
