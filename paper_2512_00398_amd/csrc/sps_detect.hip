@@ -81,9 +81,10 @@ __device__ __forceinline__ uint4 group_pack(uint64_t M, uint64_t V, int S, int m
 }
 
 // One level of the in-order combine of 16 group summaries held by the lanes
-// of a DPP row: lanes at multiples of 2D absorb the summary of lane + D.
+// of a DPP row: lanes at multiples of 2D absorb the summary of lane + D; the
+// run closed at the junction (if any) is returned in `pe`.
 template <int D>
-__device__ __forceinline__ RunSum rs_absorb(const RunSum& g, int k, bool act, const Emitter& em) {
+__device__ __forceinline__ RunSum rs_absorb(const RunSum& g, int k, bool act, Pending& pe) {
   RunSum r;
   r.flags = row_down<D>(0, g.flags);
   r.hi = row_down<D>(0, g.hi);
@@ -92,9 +93,8 @@ __device__ __forceinline__ RunSum rs_absorb(const RunSum& g, int k, bool act, co
   r.hq = row_down<D>(0.0, g.hq);
   r.tq = row_down<D>(0.0, g.tq);
   const bool mine = (k & (2 * D - 1)) == 0;
-  Emitter e = em;
-  e.writer = act && mine;
-  const RunSum c = rs_combine(g, r, e);
+  const RunSum c = rs_combine_p(g, r, pe);
+  pe.f = pe.f && act && mine;
   RunSum o;
   o.flags = mine ? c.flags : g.flags;
   o.hi = mine ? c.hi : g.hi;
@@ -103,6 +103,39 @@ __device__ __forceinline__ RunSum rs_absorb(const RunSum& g, int k, bool act, co
   o.hq = mine ? c.hq : g.hq;
   o.tq = mine ? c.tq : g.tq;
   return o;
+}
+
+// Number of lanes below this one in mask m.
+__device__ __forceinline__ int lane_prefix(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Writes the lanes' pending candidates with one LDS atomic for the whole
+// wave: records go to the LDS staging buffer, past its end to global memory.
+// E.width is the lane's own width. All lanes of the wave must call it.
+template <int NP>
+__device__ __forceinline__ void emit_batch(const Pending (&p)[NP], const Emitter& E, int lane) {
+  int off[NP];
+  int tot = 0;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const uint64_t m = ballot(p[k].f);
+    off[k] = tot + lane_prefix(m);
+    tot += popc(m);
+  }
+  if (tot == 0) return;
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(E.cbuf_n, (uint32_t)tot);
+  base = (uint32_t)readfirst((int)base);
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    if (p[k].f) {
+      const uint32_t slot = base + (uint32_t)off[k];
+      const sps_cand c = make_cand(E, p[k].i, p[k].q);
+      if (slot < (uint32_t)kCbuf) E.cbuf[slot] = c;
+      else emit_global(E, c);
+    }
+  }
 }
 
 // Window ends of width w in a step start (64 - ceil(w/2) mod 64) mod 64
@@ -133,6 +166,7 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
   __shared__ int32_t tmad[kMaxWidths][kGroups];
   __shared__ uint4 gsum[kMaxWidths][kGroups];
   __shared__ RunSum carry[kMaxWidths];
+  __shared__ double s_sqw[kMaxWidths];
   __shared__ sps_cand cbuf[2][kCbuf];
   __shared__ uint32_t wtot[2][4];
   __shared__ uint32_t step_mask, flush_n, flush_base;
@@ -209,7 +243,10 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
   fetch(0, nmk, nf0, nf1, nf2, nf3);
   prefix(0, nmk, nf0, nf1, nf2, nf3);
   if (nsteps > 1) fetch(1, nmk, nf0, nf1, nf2, nf3);
-  if (tid < nw) carry[tid] = rs_empty();
+  if (tid < nw) {
+    carry[tid] = rs_empty();
+    s_sqw[tid] = A.sqrtw[tid];
+  }
   if (tid == 0) { cbuf_n[0] = 0u; cbuf_n[1] = 0u; }
   uint32_t carryP = 0;  // P at the step's first sample
   __syncthreads();
@@ -352,14 +389,17 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
       const int slot = 4 * ((wave + c) & 3) + r;
       if (4 * ((wave + c) & 3) < nflag) {
         const bool act = slot < nflag;
-        uint32_t mm = smask;
-        for (int t = 0; t < slot && mm; ++t) mm &= mm - 1u;
-        const int j = act ? __ffs(mm) - 1 : 0;
+        // j = index of the slot-th set bit: the largest j with slot set bits below it
+        int jb = 0;
+#pragma unroll
+        for (int st = 8; st > 0; st >>= 1)
+          if (__popc(smask & ((1u << (jb + st)) - 1u)) <= slot) jb += st;
+        const int j = act ? jb : 0;
         const int w = 1 << j, sh = group_shift(w);
         const uint4 pk = gsum[j][k];
         RunSum gs = rs_empty();
         if (act) {
-          const double den = (kMadToSigma * (double)(int)pk.w) * A.sqrtw[j];
+          const double den = (kMadToSigma * (double)(int)pk.w) * s_sqw[j];
           const int i0 = s0 + cC - sh + 64 * k - w;
           gs.flags = (int)(pk.x & 15u);
           gs.hi = i0 + (int)((pk.x >> 8) & 63u);
@@ -367,17 +407,24 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
           gs.hq = (double)(int)pk.y / den;
           gs.tq = (double)(int)pk.z / den;
         }
-        const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, false,
+        const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, true,
                          A.sample_offset};
-        gs = rs_absorb<1>(gs, k, act, em);
-        gs = rs_absorb<2>(gs, k, act, em);
-        gs = rs_absorb<4>(gs, k, act, em);
-        gs = rs_absorb<8>(gs, k, act, em);
-        if (act && k == 0) {
-          Emitter e0 = em;
-          e0.writer = true;
-          carry[j] = rs_combine(carry[j], gs, e0);
-        }
+        Pending pe[1];
+        gs = rs_absorb<1>(gs, k, act, pe[0]);
+        emit_batch(pe, em, lane);
+        gs = rs_absorb<2>(gs, k, act, pe[0]);
+        emit_batch(pe, em, lane);
+        gs = rs_absorb<4>(gs, k, act, pe[0]);
+        emit_batch(pe, em, lane);
+        gs = rs_absorb<8>(gs, k, act, pe[0]);
+        emit_batch(pe, em, lane);
+        const bool owner = act && k == 0;
+        RunSum cj = rs_empty();
+        if (owner) cj = carry[j];
+        cj = rs_combine_p(cj, gs, pe[0]);
+        pe[0].f = pe[0].f && owner;
+        if (owner) carry[j] = cj;
+        emit_batch(pe, em, lane);
       }
     }
     for (int j = wave; j < nw; j += 4) {

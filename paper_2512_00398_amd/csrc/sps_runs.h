@@ -55,13 +55,30 @@ struct Emitter {
   int32_t soff;         // emitted sample = position - soff
 };
 
-__device__ __forceinline__ void emit(const Emitter& E, int32_t sample, double q) {
-  if (!E.writer) return;
+__device__ __forceinline__ sps_cand make_cand(const Emitter& E, int32_t sample, double q) {
   sps_cand c;
   c.sample = sample - E.soff;
   c.dm_idx = E.dm;
   c.width = E.width;
   c.snr = (float)q;
+  return c;
+}
+
+// Global write of one record past the LDS staging (or without staging). The
+// non-temporal store keeps the compiler from merging it with the LDS store
+// into one slower flat store.
+__device__ __forceinline__ void emit_global(const Emitter& E, const sps_cand& c) {
+  const uint32_t slot = atomicAdd(E.ncand, 1u);
+  if (slot < E.cap) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const v4i v = {c.sample, (int)c.dm_idx, (int)c.width, __float_as_int(c.snr)};
+    __builtin_nontemporal_store(v, reinterpret_cast<v4i*>(E.cands + slot));
+  }
+}
+
+__device__ __forceinline__ void emit(const Emitter& E, int32_t sample, double q) {
+  if (!E.writer) return;
+  const sps_cand c = make_cand(E, sample, q);
   if (E.cbuf) {
     const uint32_t s = atomicAdd(E.cbuf_n, 1u);
     if (s < (uint32_t)kCbuf) {
@@ -69,8 +86,7 @@ __device__ __forceinline__ void emit(const Emitter& E, int32_t sample, double q)
       return;
     }
   }
-  const uint32_t slot = atomicAdd(E.ncand, 1u);
-  if (slot < E.cap) E.cands[slot] = c;
+  emit_global(E, c);
 }
 
 __device__ __forceinline__ RunSum rs_empty() {
@@ -81,15 +97,22 @@ __device__ __forceinline__ RunSum rs_empty() {
 
 // true if the best (q1 at i1) beats (q2 at i2): larger S/N, earlier on ties.
 __device__ __forceinline__ bool beats(double q1, int i1, double q2, int i2) {
-  return q1 > q2 || (q1 == q2 && i1 < i2);
+  return (q1 > q2) | ((q1 == q2) & (i1 < i2));  // no short-circuit: no branches
 }
 
+// A candidate held back for a batched write: valid, sample, S/N.
+struct Pending {
+  bool f;
+  int i;
+  double q;
+};
+
 // Summary of range L followed immediately by range R. The run that ends at
-// the junction (touching neither end of L+R) is emitted. Written with
+// the junction (touching neither end of L+R) is returned in `out`. Written with
 // selects on scalars (never on whole summaries, which would make the
 // compiler select addresses and keep the summaries in scratch memory), so
 // lanes holding different summaries combine without branching.
-__device__ __forceinline__ RunSum rs_combine(const RunSum L, const RunSum R, const Emitter& E) {
+__device__ __forceinline__ RunSum rs_combine_p(const RunSum L, const RunSum R, Pending& out) {
   const int Lfl = L.flags, Rfl = R.flags;
   const int Lhi = L.hi, Lti = L.ti, Rhi = R.hi, Rti = R.ti;
   const double Lhq = L.hq, Ltq = L.tq, Rhq = R.hq, Rtq = R.tq;
@@ -109,7 +132,9 @@ __device__ __forceinline__ RunSum rs_combine(const RunSum L, const RunSum R, con
   // the run ending at the junction
   const bool junction = Lne && Rne && !Lf && !Rf && (Lt || Rh);
   const bool pickR = Rh && (!Lt || beats(Rhq, Rhi, Ltq, Lti));
-  if (junction) emit(E, pickR ? Rhi : Lti, pickR ? Rhq : Ltq);
+  out.f = junction;
+  out.i = pickR ? Rhi : Lti;
+  out.q = pickR ? Rhq : Ltq;
   // an empty side leaves the other unchanged
   fl = !Lne ? Rfl : (!Rne ? Lfl : fl);
   hi = !Lne ? Rhi : (!Rne ? Lhi : hi);
@@ -123,6 +148,14 @@ __device__ __forceinline__ RunSum rs_combine(const RunSum L, const RunSum R, con
   o.pad = 0;
   o.hq = hq;
   o.tq = tq;
+  return o;
+}
+
+// The same, emitting the junction run at once.
+__device__ __forceinline__ RunSum rs_combine(const RunSum L, const RunSum R, const Emitter& E) {
+  Pending p;
+  const RunSum o = rs_combine_p(L, R, p);
+  if (p.f) emit(E, p.i, p.q);
   return o;
 }
 
