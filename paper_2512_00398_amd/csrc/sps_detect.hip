@@ -282,10 +282,10 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
       cbuf_n[buf ^ 1] = 0u;
       if (fl_n) fl_base = atomicAdd(A.ncand, fl_n);
     }
+    // interior step: every position of every width is valid, no masks needed
+    const bool clean = cC - 64 >= max(A.maxw, max(e_lo0, e_lo1 + A.maxw)) &&
+                       cC + kC - 1 <= min(e_seg, e_row - A.maxw);
     {
-      // interior step: every position of every width is valid, no masks needed
-      const bool clean = cC - 64 >= max(A.maxw, max(e_lo0, e_lo1 + A.maxw)) &&
-                         cC + kC - 1 <= min(e_seg, e_row - A.maxw);
       uint32_t flagged = 0u;
       auto fast = [&](auto CLEAN) {
         int cur_shift = -1;
@@ -353,6 +353,7 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
       const int4 HI = *reinterpret_cast<const int4*>(&thi[j][4 * wave]);
       const int4 MD = *reinterpret_cast<const int4*>(&tmad[j][4 * wave]);
       int S[4], best[4];
+      bool in[4];
       uint64_t M[4], V[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -363,11 +364,24 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
         const int mad = q == 0 ? MD.x : q == 1 ? MD.y : q == 2 ? MD.z : MD.w;
         bool ab = S[q] >= hi && hi != INT_MAX;
         if (S[q] > lo && !ab) ab = (double)S[q] / ((kMadToSigma * (double)mad) * sqw) > A.theta;
-        V[q] = lane_range(vlo - eg - 64 * q, vhi - eg - 64 * q);
-        const bool in = ab && ((V[q] >> lane) & 1ull);
-        M[q] = ballot(in);
-        best[q] = wave_max_u(in ? S[q] : INT_MIN);
+        in[q] = ab;
       }
+      if (clean) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) V[q] = ~0ull;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          V[q] = lane_range(vlo - eg - 64 * q, vhi - eg - 64 * q);
+          in[q] = in[q] && ((V[q] >> lane) & 1ull);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        M[q] = ballot(in[q]);
+        best[q] = in[q] ? S[q] : INT_MIN;
+      }
+      wave_max4_u(best[0], best[1], best[2], best[3]);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int mad = q == 0 ? MD.x : q == 1 ? MD.y : q == 2 ? MD.z : MD.w;

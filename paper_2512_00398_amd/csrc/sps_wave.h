@@ -68,6 +68,29 @@ __device__ __forceinline__ int wave_max_u(int v) {
   return readlane(v, 63);
 }
 
+template <int CTRL, int RM>
+__device__ __forceinline__ void max_step4(int& a, int& b, int& c, int& d) {
+  a = max(a, dpp<CTRL, RM>(a, a));
+  b = max(b, dpp<CTRL, RM>(b, b));
+  c = max(c, dpp<CTRL, RM>(c, c));
+  d = max(d, dpp<CTRL, RM>(d, d));
+}
+
+// wave_max_u of four values at once, interleaved so that the DPP latencies
+// of the four reductions overlap.
+__device__ __forceinline__ void wave_max4_u(int& a, int& b, int& c, int& d) {
+  max_step4<0xb1, 0xf>(a, b, c, d);
+  max_step4<0x4e, 0xf>(a, b, c, d);
+  max_step4<0x141, 0xf>(a, b, c, d);
+  max_step4<0x140, 0xf>(a, b, c, d);
+  max_step4<0x142, 0xa>(a, b, c, d);
+  max_step4<0x143, 0xc>(a, b, c, d);
+  a = readlane(a, 63);
+  b = readlane(b, 63);
+  c = readlane(c, 63);
+  d = readlane(d, 63);
+}
+
 // Sum over the 64 lanes, returned wave-uniform.
 __device__ __forceinline__ int wave_sum_u(int v) { return readlane(wave_scan_incl(v), 63); }
 
