@@ -494,8 +494,11 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
 // Persistent form over a batch of blocks: workgroups take (item, segment)
 // tasks from a queue (items ordered by segment length, longest first) until
 // none is left; every workgroup leaves once the counter passes the total.
+// Four waves per SIMD (at most 128 VGPRs): reading each item's arguments from
+// memory costs registers, and the kernel is faster at this occupancy even
+// with the two spilled registers it takes.
 template <int NW>
-__global__ __launch_bounds__(256) void k_detect_batch(BatchDetect B) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_detect_batch(BatchDetect B) {
   __shared__ int s_task;
   while (true) {
     if (threadIdx.x == 0) s_task = (int)atomicAdd(B.counter, 1u);
