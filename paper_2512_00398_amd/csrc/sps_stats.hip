@@ -278,11 +278,36 @@ __device__ void exact_block(Chain<NB, VIRT>& c, int lo, int hi) {
   }
 }
 
+// Median of up to 256 samples spread evenly over [lo, hi) (four per lane):
+// a bitwise binary search on the order-preserving keys, counted with ballots.
+template <bool VIRT>
+__device__ int sample_median(const RowRef<VIRT>& row, int lo, int hi, int lane) {
+  const int n = hi - lo;
+  const int ns = n < 256 ? n : 256;
+  uint32_t k[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = lane + 64 * q;
+    k[q] = i < ns ? ((uint32_t)row.iat(lo + (int)(((int64_t)i * n) / ns)) ^ 0x80000000u) : 0xFFFFFFFFu;
+  }
+  const int rank = (ns - 1) >> 1;
+  uint32_t p = 0;  // largest key with #{k < p} <= rank
+  for (int b = 31; b >= 0; --b) {
+    const uint32_t cand = p | (1u << b);
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cnt += popc(ballot(k[q] < cand));
+    if (cnt <= rank) p = cand;
+  }
+  return (int)(p ^ 0x80000000u);
+}
+
 template <int NB, bool VIRT>
 __device__ void chain_init(Chain<NB, VIRT>& c, int lo, int hi) {
-  // Centre the first histogram on the median of the last <= 256 window samples.
-  const int slo = max(lo, hi - 256);
-  const int g = (int)(radix_select<0, VIRT>(c.H, c.row, slo, hi, (hi - slo - 1) >> 1, 0, c.lane) ^ 0x80000000u);
+  // Centre the first histogram on the median of samples spread over the
+  // whole window (a contiguous run of samples can sit far from it when the
+  // data drift).
+  const int g = sample_median(c.row, lo, hi, c.lane);
   const int below = rebuild(c, lo, hi, g - NB / 2);
   if (!full_query(c, below)) exact_block(c, lo, hi);
 }
