@@ -285,7 +285,7 @@ def main():
                          "5 serving 16 beams (literal arrival rate, then a time-compressed sweep)")
     ap.add_argument("--serve-horizon", type=float, default=20.0,
                     help="seconds of literal-rate arrivals served in --config 5")
-    ap.add_argument("--cpu-rows", type=int, default=16)
+    ap.add_argument("--cpu-rows", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain per-stage path")
     ap.add_argument("--autotune", action="store_true",

@@ -58,9 +58,11 @@ constexpr int kDetectStep = 1024;
 // Blocks per baseline chain for `nb` blocks per row (tuning only).
 int stats_seg_for(const sps_plan* p, int64_t nb) {
   if (p->stats_seg > 0) return (int)std::min<int64_t>(p->stats_seg, std::max<int64_t>(nb, 1));
-  // ~10k chains fill 256 CUs x ~20 resident waves twice over; keep each
-  // chain >= 4 windows long so the warm-up recount stays a small overhead.
-  const int64_t want_chains = 10240;
+  // ~4k chains: about one per resident wave (256 CUs x 20 waves); longer
+  // chains spend less on warm-up recounts and keep fewer windows in flight,
+  // which the re-read of samples leaving the window favours (measured).
+  // Keep each chain >= 4 windows long.
+  const int64_t want_chains = 4096;
   int64_t per_row = (want_chains + p->ndm - 1) / p->ndm;
   if (per_row < 1) per_row = 1;
   int64_t seg = (nb + per_row - 1) / per_row;
@@ -77,9 +79,9 @@ int auto_stats_seg(const sps_plan* p) { return stats_seg_for(p, p->nblocks); }
 int detect_seg_for(const sps_plan* p, int64_t npos) {
   int64_t seg = p->detect_seg;
   if (seg <= 0) {
-    // ~4096 workgroups; each segment >= 4 x max_width so the halo stays small
+    // ~8192 workgroups; each segment >= 4 x max_width so the halo stays small
     const int64_t total = (int64_t)p->ndm * npos;
-    seg = total / 4096;
+    seg = total / 8192;
     seg = std::max<int64_t>(seg, 4LL * p->max_width);
   }
   seg = ((seg + kDetectStep - 1) / kDetectStep) * kDetectStep;
@@ -1027,13 +1029,13 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
     if (b->stats_seg > 0) {
       seg = b->stats_seg;
     } else {
-      seg = (total_blocks + 10239) / 10240;
+      seg = (total_blocks + 4095) / 4096;
       seg = std::max<int64_t>(seg, std::max<int64_t>(64, (4LL * it.baseline_len + 63) / 64));
     }
     seg = std::max<int64_t>(1, std::min<int64_t>(seg, s.nblocks));
     s.stats_seg = (int32_t)seg;
     s.stats_nseg = (int32_t)((s.nblocks + seg - 1) / seg);
-    int64_t dseg = b->detect_seg > 0 ? b->detect_seg : std::max<int64_t>(total_samples / 4096, 4LL * it.max_width);
+    int64_t dseg = b->detect_seg > 0 ? b->detect_seg : std::max<int64_t>(total_samples / 8192, 4LL * it.max_width);
     dseg = (dseg + kDetectStep - 1) / kDetectStep * kDetectStep;
     const int64_t nmax = std::max<int64_t>(kDetectStep, (it.nsamp + kDetectStep - 1) / kDetectStep * kDetectStep);
     dseg = std::max<int64_t>(kDetectStep, std::min<int64_t>(dseg, nmax));
