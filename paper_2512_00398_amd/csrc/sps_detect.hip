@@ -288,11 +288,12 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
     {
       uint32_t flagged = 0u;
       auto fast = [&](auto CLEAN) {
+        // widths below 8: lane l reads window end l of each of the wave's 4 groups
         int cur_shift = -1;
         uint32_t pe[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int j = 0; j < (NW > 0 ? NW : kMaxWidths); ++j) {
-          if (NW == 0 && j >= nw) break;
+        for (int j = 0; j < 3; ++j) {
+          if (j >= nw) break;
           const int w = 1 << j, sh = group_shift(w);
           const int eg = cC - sh + 256 * wave;
           if (sh != cur_shift) {
@@ -305,10 +306,7 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int e0 = eg + 64 * q;
-            // P[E - w]: when E - w is 64-aligned the group never wraps the ring
-            const uint32_t pw = ((e0 - w) & 63) == 0 ? ring[((e0 - w) & (kRing - 1)) + lane]
-                                                     : ring[(e0 - w + lane) & (kRing - 1)];
-            const int S = (int)(pe[q] - pw);
+            const int S = (int)(pe[q] - ring[(e0 - w + lane) & (kRing - 1)]);
             const int T = q == 0 ? T4.x : q == 1 ? T4.y : q == 2 ? T4.z : T4.w;
             const uint64_t hit = ballot(S > T);
             if (CLEAN) {
@@ -320,6 +318,36 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
             }
           }
           flagged |= acc ? (1u << j) : 0u;
+        }
+        // widths 8 and up: the group shift is a multiple of 4, so lane l reads
+        // window ends 4l .. 4l+3 of the wave's 256 with one 16-byte LDS read
+        // (group l / 16)
+        int cur_sh4 = -1;
+        uint4 pe4 = make_uint4(0u, 0u, 0u, 0u);
+        const int gq = lane >> 4;
+#pragma unroll
+        for (int j = 3; j < (NW > 0 ? NW : kMaxWidths); ++j) {
+          if (NW == 0 && j >= nw) break;
+          const int w = 1 << j, sh = group_shift(w);
+          const int eg = cC - sh + 256 * wave;
+          const int e4 = eg + 4 * lane;
+          if (sh != cur_sh4) {
+            cur_sh4 = sh;
+            pe4 = *reinterpret_cast<const uint4*>(&ring[e4 & (kRing - 1)]);
+          }
+          const uint4 pw4 = *reinterpret_cast<const uint4*>(&ring[(e4 - w) & (kRing - 1)]);
+          const int T = tlo[j][4 * wave + gq];
+          bool h0 = (int)(pe4.x - pw4.x) > T, h1 = (int)(pe4.y - pw4.y) > T;
+          bool h2 = (int)(pe4.z - pw4.z) > T, h3 = (int)(pe4.w - pw4.w) > T;
+          if (!CLEAN) {
+            const int vhi = min(e_seg + w - 1, e_row);
+            const int vlo = max(w, max(e_lo0, e_lo1 + w));
+            h0 = h0 && e4 >= vlo && e4 <= vhi;
+            h1 = h1 && e4 + 1 >= vlo && e4 + 1 <= vhi;
+            h2 = h2 && e4 + 2 >= vlo && e4 + 2 <= vhi;
+            h3 = h3 && e4 + 3 >= vlo && e4 + 3 <= vhi;
+          }
+          flagged |= ballot(h0 || h1 || h2 || h3) ? (1u << j) : 0u;
         }
       };
       if (clean) fast(std::true_type{});
