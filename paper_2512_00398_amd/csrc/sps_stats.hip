@@ -229,11 +229,17 @@ __device__ __forceinline__ bool narrow_query(Chain<NB, VIRT>& c) {
   const int im = c.m - c.base, iL = c.m - c.d - c.base, iU = c.m + c.d + 1 - c.base;
   if (iL - 8 < 0 || iU + 8 > NB) return false;  // im lies between them
   const int lane = c.lane, r = lane >> 4, k = lane & 15;
-  const int ib = r == 0 ? im : (r == 1 ? iL : iU);
+  // per-row selects written as a chain of two-way selects (a nested
+  // conditional on scalar operands compiles to branches)
+  int ib = iU;
+  ib = r == 1 ? iL : ib;
+  ib = r == 0 ? im : ib;
   const int h = hist_get(c.H, ib - 8 + k);
   const int inc = row_scan_incl(h);
   const int i0 = readlane(inc, 7), i1 = readlane(inc, 23), i2 = readlane(inc, 39);
-  const int cb = r == 0 ? c.cm - i0 : (r == 1 ? c.cL - i1 : c.cU - i2);
+  int cb = c.cU - i2;
+  cb = r == 1 ? c.cL - i1 : cb;
+  cb = r == 0 ? c.cm - i0 : cb;
   const int lt = cb + inc - h;  // #{x < pivot - 8 + k} in rows 0..2
   const uint64_t mk = ballot(lt + h > rho) & 0xFFFFull;
   if (!mk) return false;       // median above the window
@@ -340,7 +346,11 @@ __device__ void slow_block(Chain<NB, VIRT>& c, int lo, int hi) {
 
 template <int NB, bool VIRT>
 __device__ __forceinline__ void chain_step(Chain<NB, VIRT>& c, int lo, int hi, bool a_ok, int av, bool b_ok, int bv) {
-  c.n += popc(ballot(a_ok)) - popc(ballot(b_ok));
+  // lane masks of the entering (a) and leaving (b) samples; the counts below
+  // AND raw comparison ballots with them (a comparison's ballot is its own
+  // lane mask, a combined condition would be materialised and compared again)
+  const uint64_t aM = ballot(a_ok), bM = ballot(b_ok);
+  c.n += popc(aM) - popc(bM);
   if (c.raw) {
     exact_block(c, lo, hi);
     return;
@@ -349,9 +359,9 @@ __device__ __forceinline__ void chain_step(Chain<NB, VIRT>& c, int lo, int hi, b
   if (a_ok && ua < (uint32_t)NB) hist_add(c.H, ua, 1u);
   if (b_ok && ub < (uint32_t)NB) hist_add(c.H, ub, 0xFFFFFFFFu);
   const int pL = c.m - c.d, pU = c.m + c.d + 1;
-  c.cm += popc(ballot(a_ok && av < c.m)) - popc(ballot(b_ok && bv < c.m));
-  c.cL += popc(ballot(a_ok && av < pL)) - popc(ballot(b_ok && bv < pL));
-  c.cU += popc(ballot(a_ok && av < pU)) - popc(ballot(b_ok && bv < pU));
+  c.cm += popc(ballot(av < c.m) & aM) - popc(ballot(bv < c.m) & bM);
+  c.cL += popc(ballot(av < pL) & aM) - popc(ballot(bv < pL) & bM);
+  c.cU += popc(ballot(av < pU) & aM) - popc(ballot(bv < pU) & bM);
   wave_lds_fence();
   if (!narrow_query(c) && !fast_query(c)) slow_block(c, lo, hi);
 }
