@@ -337,17 +337,20 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
           }
           const uint4 pw4 = *reinterpret_cast<const uint4*>(&ring[(e4 - w) & (kRing - 1)]);
           const int T = tlo[j][4 * wave + gq];
-          bool h0 = (int)(pe4.x - pw4.x) > T, h1 = (int)(pe4.y - pw4.y) > T;
-          bool h2 = (int)(pe4.z - pw4.z) > T, h3 = (int)(pe4.w - pw4.w) > T;
+          int d0 = (int)(pe4.x - pw4.x), d1 = (int)(pe4.y - pw4.y);
+          int d2 = (int)(pe4.z - pw4.z), d3 = (int)(pe4.w - pw4.w);
           if (!CLEAN) {
             const int vhi = min(e_seg + w - 1, e_row);
             const int vlo = max(w, max(e_lo0, e_lo1 + w));
-            h0 = h0 && e4 >= vlo && e4 <= vhi;
-            h1 = h1 && e4 + 1 >= vlo && e4 + 1 <= vhi;
-            h2 = h2 && e4 + 2 >= vlo && e4 + 2 <= vhi;
-            h3 = h3 && e4 + 3 >= vlo && e4 + 3 <= vhi;
+            d0 = (e4 >= vlo && e4 <= vhi) ? d0 : INT_MIN;
+            d1 = (e4 + 1 >= vlo && e4 + 1 <= vhi) ? d1 : INT_MIN;
+            d2 = (e4 + 2 >= vlo && e4 + 2 <= vhi) ? d2 : INT_MIN;
+            d3 = (e4 + 3 >= vlo && e4 + 3 <= vhi) ? d3 : INT_MIN;
           }
-          flagged |= ballot(h0 || h1 || h2 || h3) ? (1u << j) : 0u;
+          // one comparison of the largest of the four (no short-circuit: a
+          // logical or lets the compiler split the load and branch)
+          const int dm = max(max(d0, d1), max(d2, d3));
+          flagged |= ballot(dm > T) ? (1u << j) : 0u;
         }
       };
       if (clean) fast(std::true_type{});
