@@ -105,6 +105,17 @@ int sps_search(sps_plan* plan, const float* d_series, hipStream_t stream, sps_ca
                uint32_t* d_ncand);
 
 /*
+ * Input domain (every search entry point): each sample integer-valued with
+ * |x| <= sps_domain_bound(max_width) = min(2^24 - 1, (2^31 - 1) / (2 *
+ * max_width)), so that the conversion to integers is exact and every boxcar
+ * sum of residuals fits in int32. Outside it results are unspecified. With
+ * SPS_ATTR_VALIDATE = 1 every search (and stream push) first checks its input
+ * on the device, waits for the answer, and returns SPS_ERR_DOMAIN without
+ * searching if a sample falls outside (a debug mode: host-synchronous).
+ */
+int64_t sps_domain_bound(int32_t max_width);
+
+/*
  * Baseline-removal and normalisation stages only: write m_k and MAD_k of
  * every block of every row to d_median and d_mad (device int32
  * [ndm][ceil(nsamp/64)], row stride ceil(nsamp/64)). Section II-B,
@@ -130,6 +141,7 @@ int sps_search_plain(sps_plan* plan, const float* d_series, hipStream_t stream, 
 #define SPS_ATTR_DETECT_SEG 3     /* samples per detection segment, multiple of 1024 (0 = auto) */
 #define SPS_ATTR_HIST_BINS 4      /* fine histogram span in values: 4096 or 16384 (tuning) */
 #define SPS_ATTR_TIMING 5         /* 1: record HIP events around every kernel of a search */
+#define SPS_ATTR_VALIDATE 6       /* 1: check the input domain before each search (host-synchronous) */
 #define SPS_ATTR_NBLOCKS 16       /* read-only: ceil(nsamp / 64) */
 #define SPS_ATTR_NWIDTHS 17       /* read-only: number of boxcar widths */
 

@@ -31,6 +31,9 @@ struct sps_plan {
   // plain per-stage path scratch (allocated on first use)
   void* d_plain;
   size_t plain_bytes;
+  // debug: check the input domain before each search
+  int validate;
+  uint32_t* d_flag;    // 1 word: the domain check's answer
   // tracing: events recorded around kernels when timing is on
   int timing;
   std::vector<hipEvent_t>* ev_free;
@@ -130,6 +133,26 @@ int64_t frag_need(const sps_plan* p) {
   return nseg > 1 ? (int64_t)p->ndm * p->nw * nseg : 0;
 }
 
+int64_t domain_bound(int32_t max_width) {
+  const int64_t b = (int64_t)INT32_MAX / (2LL * (max_width > 0 ? max_width : 1));
+  return b < (1LL << 24) - 1 ? b : (1LL << 24) - 1;
+}
+
+// SPS_ATTR_VALIDATE: check n samples at x on the device and wait for the
+// answer. SPS_OK, SPS_ERR_DOMAIN or SPS_ERR_HIP.
+int check_domain(sps_plan* p, const float* x, int64_t n, hipStream_t s) {
+  if (!p->validate) return SPS_OK;
+  uint32_t h = 0;
+  if (sps::launch_zero_u32(p->d_flag, 1, s) != hipSuccess ||
+      sps::launch_validate(x, n, (float)domain_bound(p->max_width), p->d_flag, s) != hipSuccess ||
+      hipMemcpyAsync(&h, p->d_flag, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipGetLastError();
+    return SPS_ERR_HIP;
+  }
+  return h ? SPS_ERR_DOMAIN : SPS_OK;
+}
+
 int ensure_frag(sps_plan* p) {
   const int64_t need = frag_need(p);
   if (need <= p->frag_cap) return SPS_OK;
@@ -212,7 +235,8 @@ sps_plan* sps_plan_create(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t
     return nullptr;
   }
   const size_t stats_bytes = (size_t)ndm * p->nblocks * sizeof(int32_t);
-  if (hipMalloc(&p->d_med, stats_bytes) != hipSuccess || hipMalloc(&p->d_mad, stats_bytes) != hipSuccess) {
+  if (hipMalloc(&p->d_med, stats_bytes) != hipSuccess || hipMalloc(&p->d_mad, stats_bytes) != hipSuccess ||
+      hipMalloc(&p->d_flag, sizeof(uint32_t)) != hipSuccess) {
     (void)hipGetLastError();
     sps_plan_destroy(p);
     fail(SPS_ERR_OOM);
@@ -234,6 +258,7 @@ void sps_plan_destroy(sps_plan* p) {
   if (p->d_mad) (void)hipFree(p->d_mad);
   if (p->d_frag) (void)hipFree(p->d_frag);
   if (p->d_plain) (void)hipFree(p->d_plain);
+  if (p->d_flag) (void)hipFree(p->d_flag);
   if (p->ev_pending) {
     for (auto& e : *p->ev_pending) {
       (void)hipEventDestroy(e.second.first);
@@ -298,6 +323,10 @@ int sps_plan_set(sps_plan* p, int attr, int64_t v) {
       if (v != 0 && v != 1) return fail(SPS_ERR_INVALID_ARG);
       p->timing = (int)v;
       return ok();
+    case SPS_ATTR_VALIDATE:
+      if (v != 0 && v != 1) return fail(SPS_ERR_INVALID_ARG);
+      p->validate = (int)v;
+      return ok();
     default:
       return fail(SPS_ERR_INVALID_ARG);
   }
@@ -311,6 +340,7 @@ int sps_plan_get(const sps_plan* p, int attr, int64_t* v) {
     case SPS_ATTR_DETECT_SEG: *v = auto_detect_seg(p); break;
     case SPS_ATTR_HIST_BINS: *v = p->hist_bins; break;
     case SPS_ATTR_TIMING: *v = p->timing; break;
+    case SPS_ATTR_VALIDATE: *v = p->validate; break;
     case SPS_ATTR_NBLOCKS: *v = p->nblocks; break;
     case SPS_ATTR_NWIDTHS: *v = p->nw; break;
     default: return fail(SPS_ERR_INVALID_ARG);
@@ -357,6 +387,10 @@ int sps_search(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand*
   d.seg_len = auto_detect_seg(p);
   d.nseg = (p->nsamp + d.seg_len - 1) / d.seg_len;
   if (d.nseg > 1 && (int64_t)p->ndm * p->nw * d.nseg > p->frag_cap) return fail(SPS_ERR_INVALID_ARG);
+  {
+    const int rc = check_domain(p, d_series, (int64_t)p->ndm * p->nsamp, stream);
+    if (rc != SPS_OK) return fail(rc);
+  }
   hipEvent_t e0 = mark(p, stream);
   if (sps::launch_zero_u32(d_ncand, 1, stream) != hipSuccess) return fail(SPS_ERR_HIP);
   hipEvent_t e1 = mark(p, stream);
@@ -400,6 +434,10 @@ int sps_search(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand*
 
 int sps_search_plain(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand) {
   if (!p || !d_series || !d_ncand || (!d_cands && p->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+  {
+    const int rc = check_domain(p, d_series, (int64_t)p->ndm * p->nsamp, stream);
+    if (rc != SPS_OK) return fail(rc);
+  }
   const int strip = 4096;  // positions per wave in the peak stage
   const int nstrip = (p->nsamp + strip - 1) / strip;
   const size_t n = (size_t)p->ndm * p->nsamp;
@@ -722,6 +760,10 @@ extern "C" {
 int sps_stream_push(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand,
                     int64_t* gulp_offset) {
   if (!s || !d_gulp || !d_ncand || (!d_cands && s->plan->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+  {
+    const int rc = check_domain(s->plan, d_gulp, (int64_t)s->plan->ndm * s->plan->nsamp, stream);
+    if (rc != SPS_OK) return fail(rc);
+  }
   const int rc = stream_enqueue(s, d_gulp, stream, d_cands, d_ncand, s->cur, true);
   if (rc != SPS_OK) return fail(rc);
   if (gulp_offset) *gulp_offset = s->pushed;
@@ -733,6 +775,10 @@ int sps_stream_push(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_
 int sps_stream_push_graph(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands,
                           uint32_t* d_ncand, int64_t* gulp_offset) {
   if (!s || !d_gulp || !d_ncand || (!d_cands && s->plan->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+  {
+    const int rc = check_domain(s->plan, d_gulp, (int64_t)s->plan->ndm * s->plan->nsamp, stream);
+    if (rc != SPS_OK) return fail(rc);
+  }
   sps_stream::GraphEntry* hit = nullptr;
   for (auto& e : s->graphs)
     if (e.exec[0] && e.key[0] == d_gulp && e.key[1] == d_cands && e.key[2] == d_ncand) hit = &e;
@@ -862,6 +908,8 @@ int sps_stream_restore(sps_stream* s, hipStream_t stream, const void* host_buf, 
 }  // extern "C"
 
 extern "C" {
+
+int64_t sps_domain_bound(int32_t max_width) { return domain_bound(max_width); }
 
 int sps_footprint(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baseline_len, int streaming,
                   uint64_t* bytes) {

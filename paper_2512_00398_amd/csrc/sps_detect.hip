@@ -642,6 +642,17 @@ __global__ __launch_bounds__(256) void k_stream_advance(StreamArgs A) {
   if (row == 0 && blockIdx.x == 0 && threadIdx.x == 0) *A.tmin = max(0, *A.tmin - A.ngulp);
 }
 
+// Domain check: *bad = 1 if a sample is not an integer or |x| > bound
+// (NaN and infinities fail both tests).
+__global__ __launch_bounds__(256) void k_validate(const float* x, int64_t n, float bound, uint32_t* bad) {
+  bool ok = true;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = x[i];
+    ok = ok && fabsf(v) <= bound && v == rintf(v);
+  }
+  if (!ok) *bad = 1u;
+}
+
 __global__ void k_zero_u32(uint32_t* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -718,6 +729,13 @@ hipError_t launch_fixup_batch(const BatchDetect& b, const int32_t* d_offs, int t
 hipError_t launch_batch_zero(uint32_t* const* d_ncand, int n, uint32_t* counters, hipStream_t s) {
   const int m = n > 2 ? n : 2;
   hipLaunchKernelGGL(k_batch_zero, dim3((m + 255) / 256), dim3(256), 0, s, d_ncand, n, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const float* x, int64_t n, float bound, uint32_t* bad, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_validate, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, x, n, bound, bad);
   return hipGetLastError();
 }
 

@@ -150,6 +150,7 @@ hipError_t launch_block_stats(const StatsArgs& a, int hist_bins, hipStream_t s);
 hipError_t launch_detect(const DetectArgs& a, hipStream_t s);
 hipError_t launch_fixup(const DetectArgs& a, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
+hipError_t launch_validate(const float* x, int64_t n, float bound, uint32_t* bad, hipStream_t s);
 hipError_t launch_stream_fold(const StreamArgs& a, hipStream_t s);
 hipError_t launch_stream_advance(const StreamArgs& a, hipStream_t s);
 hipError_t launch_stream_close(const StreamArgs& a, hipStream_t s);

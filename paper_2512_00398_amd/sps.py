@@ -27,6 +27,7 @@ ATTR_STATS_SEG = 2
 ATTR_DETECT_SEG = 3
 ATTR_HIST_BINS = 4
 ATTR_TIMING = 5
+ATTR_VALIDATE = 6
 NSTAGES = 4
 STAGES = ("block_stats", "detect", "fixup", "plain")
 ATTR_NBLOCKS = 16
@@ -54,6 +55,7 @@ EXPORTS = [
     ("sps_stream_save", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64]),
     ("sps_stream_restore", ctypes.c_int, [_P, _P, _P, ctypes.c_uint64]),
     ("sps_stream_destroy", None, [_P]),
+    ("sps_domain_bound", ctypes.c_int64, [ctypes.c_int32]),
     ("sps_footprint", ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
                                      ctypes.POINTER(ctypes.c_uint64)]),
     ("sps_batch_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p)]),
@@ -272,6 +274,11 @@ class Stream:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def domain_bound(max_width: int) -> int:
+    """Largest |sample| the search accepts for this max_width (include/sps.h)."""
+    return int(load().sps_domain_bound(int(max_width)))
 
 
 def footprint(ndm: int, nsamp: int, max_width: int, baseline_len: int, streaming: bool = False) -> int:

@@ -74,3 +74,13 @@ def test_footprint_query_without_device():
     for bad in ((0, 16384, 64, 4096, False), (4, 100, 3, 10, False), (4, 100, 4, 10, True)):
         with pytest.raises(sps.SpsError):
             sps.footprint(*bad)
+
+
+def test_domain_bound():
+    from paper_2512_00398_amd import sps
+    # |S| <= max_width * 2 * bound must fit int32, and floats must stay exact (< 2^24)
+    for w in (1, 2, 64, 128, 256, 1024, 4096):
+        b = sps.domain_bound(w)
+        assert b <= (1 << 24) - 1
+        assert 2 * w * b <= 2 ** 31 - 1
+        assert b == (1 << 24) - 1 or 2 * w * (b + 1) > 2 ** 31 - 1

@@ -206,3 +206,50 @@ def test_large_config_sampled_rows():
     assert got["dm_idx"].max() < cfg.ndm and (got["sample"] >= 0).all()
     assert (got["sample"].astype(np.int64) + got["width"] <= cfg.nsamp).all()
     assert (got["snr"] >= np.float32(cfg.snr_thresh)).all()  # FP64 S/N > theta may round to theta in FP32
+
+
+def test_domain_validation_mode():
+    torch = _torch()
+    m = sps()
+    cfg = synth.config(1)["blocks"][0]
+    x = synth.generate(cfg)
+    with m.Plan(cfg.ndm, cfg.nsamp, cfg.max_width, cfg.baseline_len, cfg.snr_thresh) as p:
+        p.set(m.ATTR_VALIDATE, 1)
+        assert p.get(m.ATTR_VALIDATE) == 1
+        c, n = p.alloc_cands()
+        p.search(to_dev(x), c, n)
+        torch.cuda.synchronize()
+        ref = oracle.search(x, cfg.max_width, cfg.baseline_len, cfg.snr_thresh)
+        assert exact_equal(m.cands_to_numpy(c, n, p.max_cands), ref)
+        bound = m.domain_bound(cfg.max_width)
+        for bad in (0.5, float(bound + 1), -float(bound + 1), float("nan"), float("inf")):
+            y = x.copy()
+            y[cfg.ndm - 1, cfg.nsamp - 1] = bad
+            print("validate rejects", bad, flush=True)
+            n.fill_(12345)
+            with pytest.raises(m.SpsError) as e:
+                p.search(to_dev(y), c, n)
+            assert e.value.code == m.SPS_ERR_DOMAIN
+            for plain in (True,):
+                with pytest.raises(m.SpsError):
+                    p.search(to_dev(y), c, n, plain=plain)
+            torch.cuda.synchronize()
+            assert int(n.item()) == 12345  # nothing was enqueued
+        y = x.copy()
+        y[0, 0] = float(bound)  # the bound itself is inside the domain
+        p.search(to_dev(y), c, n)
+        torch.cuda.synchronize()
+
+
+def test_maximum_window_and_many_short_rows():
+    rng = np.random.default_rng(11)
+    # the largest baseline window over rows longer than it
+    x = np.round(rng.normal(5000, 300, size=(2, 150000)))
+    x[:, 90000:90040] += 700
+    got, ref, ex = check(x.astype(np.float32), 1024, 65535, 5.0, "L=65535")
+    assert ex == 0 and exact_equal(got, ref) and ref.size > 0
+    # many short rows: one chain and one detection segment per row
+    x = np.round(rng.normal(100, 10, size=(3000, 130)))
+    x[::7, 60:64] += 60
+    got, ref, ex = check(x.astype(np.float32), 64, 100, 4.0, "3000x130")
+    assert ex == 0 and exact_equal(got, ref) and ref.size > 0

@@ -195,3 +195,25 @@ def test_graph_rotating_buffers_equal_one_shot():
         out.append(a)
         st.close()
     assert exact_equal(oracle.sort_cands(np.concatenate(out)), ref)
+
+
+def test_stream_validation_rejects_bad_gulp():
+    import torch
+    m = sps()
+    x = np.zeros((2, 1024), dtype=np.float32)
+    with m.Plan(2, 1024, 64, 300, 5.0) as p:
+        p.set(m.ATTR_VALIDATE, 1)
+        c, n = p.alloc_cands()
+        st = m.Stream(p)
+        assert st.push(torch.from_numpy(x).cuda(), c, n) == 0
+        x[1, 5] = 0.25
+        with pytest.raises(m.SpsError) as e:
+            st.push(torch.from_numpy(x).cuda(), c, n)
+        assert e.value.code == m.SPS_ERR_DOMAIN
+        with pytest.raises(m.SpsError):
+            st.push(torch.from_numpy(x).cuda(), c, n, graph=True)
+        # the rejected gulp was not pushed: the next one continues at 1024
+        x[1, 5] = 0.0
+        assert st.push(torch.from_numpy(x).cuda(), c, n) == 1024
+        torch.cuda.synchronize()
+        st.close()
