@@ -253,3 +253,30 @@ def test_maximum_window_and_many_short_rows():
     x[::7, 60:64] += 60
     got, ref, ex = check(x.astype(np.float32), 64, 100, 4.0, "3000x130")
     assert ex == 0 and exact_equal(got, ref) and ref.size > 0
+
+
+def test_noise_only_false_alarm_rate_on_gpu():
+    # Closed-form check of the kernel path itself (no oracle): drift-free
+    # integer Gaussian noise, 1024 x 2^20 samples, width 1. Positions after
+    # the first L samples (full windows) exceed theta with probability
+    # Q(theta); at 5 and 5.5 sigma adjacent exceedances are vanishingly rare,
+    # so the candidate count is Poisson(N_eff * Q(theta)): ~303 and ~20.
+    import math
+    from scipy.stats import norm
+    torch = _torch()
+    m = sps()
+    b = synth.Block(ndm=1024, nsamp=1 << 20, max_width=1, baseline_len=16384, seed=20251299,
+                    drift_amp_sigma=0.0)
+    xd = to_dev(synth.generate(b))
+    neff = b.ndm * (b.nsamp - b.baseline_len)
+    for th in (5.0, 5.5):
+        with m.Plan(b.ndm, b.nsamp, 1, b.baseline_len, th) as p:
+            c, n = p.alloc_cands()
+            p.search(xd, c, n)
+            torch.cuda.synchronize()
+            got = m.cands_to_numpy(c, n, p.max_cands)
+        cnt = int((got["sample"] >= b.baseline_len).sum())
+        lam = neff * norm.sf(th)
+        z = (cnt - lam) / math.sqrt(lam)
+        print("theta %.1f: %d candidates, expected %.1f, z = %.2f" % (th, cnt, lam, z), flush=True)
+        assert abs(z) < 4.0, (th, cnt, lam, z)
