@@ -276,7 +276,7 @@ def bench_serve(args):
     def run(compress, **kw):
         arr = serve.poisson_arrivals(specs, rate, seed, **kw)
         ex = serve.GpuExecutor(source, nstreams=4, cand_cap=1 << 23)
-        rep = serve.serve(specs, arr, ex, budget, compress=compress)
+        rep = serve.serve(specs, arr, ex, budget, compress=compress, slots=args.serve_slots)
         s = rep.summary()
         s["compress"] = "inf" if compress == float("inf") else compress
         s["offered_samples_per_s"] = (sum(specs[a.beam].ndm * specs[a.beam].nsamp for a in arr) /
@@ -298,8 +298,8 @@ def bench_serve(args):
         "steps": sat["gulps"], "warmup": args.warmup, "ms_per_step": sat["wall_s"] * 1e3 / sat["gulps"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
         "config": {"workload": "%s: 16 beams, ndm 512..2048, gulps 2^16..2^18, widths=1..4096, baseline=16384, "
-                               "theta=6, Poisson arrivals at %.1fx real time, budget %d B" %
-                               (cfg["name"], rate, budget),
+                               "theta=6, Poisson arrivals at %.1fx real time, budget %d B, %d gulps in flight" %
+                               (cfg["name"], rate, budget, args.serve_slots),
                    "value_is": "saturation throughput (all arrivals at once), gulp = step"},
         "latency_literal_rate": literal,
         "latency_sweep": sweep,
@@ -319,6 +319,7 @@ def main():
                          "5 serving 16 beams (literal arrival rate, then a time-compressed sweep)")
     ap.add_argument("--serve-horizon", type=float, default=20.0,
                     help="seconds of literal-rate arrivals served in --config 5")
+    ap.add_argument("--serve-slots", type=int, default=8, help="gulps in flight at most in --config 5")
     ap.add_argument("--cpu-rows", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain per-stage path")

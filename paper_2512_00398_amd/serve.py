@@ -11,10 +11,12 @@ The scheduler is plain host logic and runs against any executor:
 - Admission: a beam is admitted when its device footprint (plan + stream +
   input and candidate buffers) fits in what is left of the memory budget;
   otherwise it waits, first come first served, until admitted beams finish.
-- Dispatch: every arriving gulp of an admitted beam is enqueued at once
-  (continuous: no batch is formed or waited for). A beam's gulps stay in order
-  on the device stream the beam is bound to; beams are spread over a few
-  device streams so that gulps of different beams overlap on the GPU.
+- Dispatch: every arriving gulp of an admitted beam is enqueued as soon as
+  one of `slots` in-flight places is free (continuous: no batch is formed or
+  waited for; arrivals beyond the slots wait first come first served). A
+  beam's gulps stay in order on the device stream the beam is bound to; beams
+  are spread over a few device streams so that gulps of different beams
+  overlap on the GPU.
 - Latency of a gulp: from its arrival to the completion of its search on the
   device (candidates in device memory).
 
@@ -130,6 +132,7 @@ class Report:
     wall: float
     samples: int
     max_concurrent_bytes: int
+    max_inflight: int = 0
 
     def latencies(self) -> np.ndarray:
         return np.array([r.latency for r in self.records], dtype=np.float64)
@@ -140,20 +143,22 @@ class Report:
                 "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
                 "max_ms": float(lat.max() * 1e3) if lat.size else None, "wall_s": self.wall,
                 "samples_per_s": self.samples / self.wall if self.wall > 0 else None,
-                "max_admitted_bytes": self.max_concurrent_bytes}
+                "max_admitted_bytes": self.max_concurrent_bytes, "max_inflight": self.max_inflight}
 
 
 def serve(specs: Sequence[BeamSpec], arrivals: Sequence[Arrival], executor, budget: int, compress: float = 1.0,
-          clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep) -> Report:
+          clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
+          slots: Optional[int] = None) -> Report:
     """Run the arrivals through the executor; compress > 1 speeds the arrival clock up
-    (float('inf'): everything arrives at once)."""
+    (float('inf'): everything arrives at once); slots caps the gulps in flight."""
     left = collections.Counter(a.beam for a in arrivals)
     adm = Admission(budget)
     backlog: Dict[int, collections.deque] = collections.defaultdict(collections.deque)
     records: List[GulpRecord] = []
     inflight: Dict[int, GulpRecord] = {}
     pending = collections.deque(sorted(arrivals, key=lambda a: (a.t, a.beam, a.k)))
-    state = {"max_used": 0, "samples": 0}
+    ready: collections.deque = collections.deque()  # admitted, waiting for a slot
+    state = {"max_used": 0, "samples": 0, "max_inflight": 0}
     t0 = clock()
     executor.start(t0)
 
@@ -168,24 +173,30 @@ def serve(specs: Sequence[BeamSpec], arrivals: Sequence[Arrival], executor, budg
         executor.submit(rec, specs[a.beam])
         inflight[id(rec)] = rec
         state["samples"] += specs[a.beam].ndm * specs[a.beam].nsamp
+        state["max_inflight"] = max(state["max_inflight"], len(inflight))
+
+    def dispatch() -> None:
+        while ready and (slots is None or len(inflight) < slots):
+            submit(*ready.popleft())
 
     def admit(beams: List[int]) -> None:
         for b in beams:
             executor.open(b, specs[b])
             state["max_used"] = max(state["max_used"], adm.used)
             while backlog[b]:
-                submit(*backlog[b].popleft())
+                ready.append(backlog[b].popleft())
 
-    while pending or inflight:
+    while pending or inflight or ready:
         tn = now()
         while pending and due(pending[0]) <= tn:
             a = pending.popleft()
             if a.beam in adm.admitted:
-                submit(a, due(a))
+                ready.append((a, due(a)))
             else:
                 backlog[a.beam].append((a, due(a)))
                 adm.enqueue(a.beam, executor.footprint(specs[a.beam]))
                 admit(adm.drain())
+        dispatch()
         for rec in executor.poll():
             del inflight[id(rec)]
             records.append(rec)
@@ -193,7 +204,8 @@ def serve(specs: Sequence[BeamSpec], arrivals: Sequence[Arrival], executor, budg
             if left[rec.beam] == 0:
                 executor.close(rec.beam)
                 admit(adm.release(rec.beam))
-        if pending and not inflight:
+        dispatch()
+        if pending and not inflight and not ready:
             sleep(max(0.0, min(due(pending[0]) - now(), 1e-3)))
         elif inflight:
             sleep(5e-5)
@@ -202,7 +214,9 @@ def serve(specs: Sequence[BeamSpec], arrivals: Sequence[Arrival], executor, budg
     wall = now()
     executor.stop()
     records.sort(key=lambda r: (r.beam, r.k))
-    return Report(records, wall, state["samples"], state["max_used"])
+    rep = Report(records, wall, state["samples"], state["max_used"])
+    rep.max_inflight = state["max_inflight"]
+    return rep
 
 
 class GpuExecutor:

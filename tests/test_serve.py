@@ -175,3 +175,15 @@ def test_beam_in_mix_equals_alone_and_oracle():
         assert exact_equal(mix, alone), b
         ref = oracle.search(xs[b], blocks[b].max_width, blocks[b].baseline_len, 5.0)
         assert exact_equal(mix, ref), b
+
+
+def test_serve_slots_cap_inflight_and_keep_order():
+    clk = FakeClock()
+    sp = specs4()
+    ex = SimExecutor(clk, rate=1e9, foot=1)
+    arr = serve.poisson_arrivals(sp, 1.5, seed=21, gulps_per_beam=8)
+    rep = serve.serve(sp, arr, ex, 10 ** 9, compress=float("inf"), clock=clk, sleep=clk.sleep, slots=3)
+    assert len(rep.records) == len(arr)
+    assert rep.max_inflight == 3
+    for b in range(len(sp)):
+        assert ex.order[b] == list(range(8))
