@@ -323,6 +323,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain per-stage path")
+    ap.add_argument("--per-dm-rows", type=int, default=32,
+                    help="rows timed for the per-DM-trial loop of the plain path (0: skip)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the plan's speed-only attributes on the input first (untimed; cached as JSON)")
     ap.add_argument("--mode", default="search", choices=["search", "copy"],
@@ -414,6 +416,23 @@ def main():
         if n_plain != n:
             raise SystemExit("plain and fused candidate counts differ: %d vs %d" % (n_plain, n))
 
+    # the plain path as a per-DM-trial loop (one row per call, the shape of the
+    # staged per-trial loop), timed on a sample of rows and scaled to ndm rows
+    per_dm_ms = None
+    if not args.no_plain and args.per_dm_rows > 0:
+        rows = min(args.per_dm_rows, b.ndm)
+        p1 = sps.Plan(1, b.nsamp, b.max_width, b.baseline_len, b.snr_thresh)
+        c1, n1 = p1.alloc_cands()
+        p1.search(xd[0:1], c1, n1, stream=stream, plain=True)
+        torch.cuda.synchronize()
+        tq0 = time.perf_counter()
+        for r in range(rows):
+            p1.search(xd[r:r + 1], c1, n1, stream=stream, plain=True)
+        torch.cuda.synchronize()
+        per_dm_ms = (time.perf_counter() - tq0) * 1e3 / rows * b.ndm
+        p1.close()
+        log("plain per-DM loop: %.1f ms per %d rows (from %d rows)" % (per_dm_ms, b.ndm, rows))
+
     samples = b.ndm * b.nsamp
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = samples * args.steps / (t1 - t0)
@@ -449,6 +468,8 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in avg.items() if k != "plain"},
         "plain_ms_per_step": plain_ms,
         "fused_vs_plain": (plain_ms / ms_per_step) if plain_ms else None,
+        "plain_per_dm_loop_ms_per_step": per_dm_ms,
+        "fused_vs_per_dm_loop": (per_dm_ms / ms_per_step) if per_dm_ms else None,
         "candidates": n,
         "tuning": tuned["config"] if tuned else "library defaults",
         "cpu_baseline": cpu,
