@@ -144,6 +144,7 @@ int sps_search_plain(sps_plan* plan, const float* d_series, hipStream_t stream, 
 #define SPS_ATTR_VALIDATE 6       /* 1: check the input domain before each search (host-synchronous) */
 #define SPS_ATTR_NBLOCKS 16       /* read-only: ceil(nsamp / 64) */
 #define SPS_ATTR_NWIDTHS 17       /* read-only: number of boxcar widths */
+#define SPS_ATTR_BLOCK_STRIDE 18  /* read-only: S = SPS_BLOCK_STRIDE, part of the arithmetic (never tuned) */
 
 /* Tuning attributes never change results, only speed. Returns SPS_OK or
  * SPS_ERR_INVALID_ARG (unknown attribute, value out of range, read-only). */

@@ -342,6 +342,7 @@ int sps_plan_get(const sps_plan* p, int attr, int64_t* v) {
     case SPS_ATTR_TIMING: *v = p->timing; break;
     case SPS_ATTR_VALIDATE: *v = p->validate; break;
     case SPS_ATTR_NBLOCKS: *v = p->nblocks; break;
+    case SPS_ATTR_BLOCK_STRIDE: *v = sps::kStride; break;
     case SPS_ATTR_NWIDTHS: *v = p->nw; break;
     default: return fail(SPS_ERR_INVALID_ARG);
   }

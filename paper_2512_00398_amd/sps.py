@@ -32,6 +32,7 @@ NSTAGES = 4
 STAGES = ("block_stats", "detect", "fixup", "plain")
 ATTR_NBLOCKS = 16
 ATTR_NWIDTHS = 17
+ATTR_BLOCK_STRIDE = 18
 
 BLOCK_STRIDE = 64
 CAND_DTYPE = np.dtype([("sample", "<i4"), ("dm_idx", "<u4"), ("width", "<u4"), ("snr", "<f4")])

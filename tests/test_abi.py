@@ -84,3 +84,43 @@ def test_domain_bound():
         assert b <= (1 << 24) - 1
         assert 2 * w * b <= 2 ** 31 - 1
         assert b == (1 << 24) - 1 or 2 * w * (b + 1) > 2 ** 31 - 1
+
+
+C_PROGRAM = r"""
+#include <stdio.h>
+#include "sps.h"
+int main(void) {
+  sps_plan* p = sps_plan_create(0, 100, 4, 10, 6.0f);
+  if (p != NULL || sps_last_error() != SPS_ERR_INVALID_ARG) return 1;
+  if (sps_search(NULL, NULL, NULL, NULL, NULL) != SPS_ERR_INVALID_ARG) return 2;
+  if (sps_domain_bound(4096) != 262143) return 3;
+  uint64_t bytes = 0;
+  if (sps_footprint(64, 16384, 64, 4096, 0, &bytes) != SPS_OK || bytes == 0) return 4;
+  sps_plan_destroy(NULL);
+  sps_batch_destroy(NULL);
+  printf("%s\n", sps_error_string(SPS_ERR_DOMAIN));
+  return 0;
+}
+"""
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    # The boundary is a C ABI: a C99 program compiles against include/sps.h,
+    # links libsps.so and calls it (argument errors only; no device needed).
+    import shutil
+    import subprocess
+    from paper_2512_00398_amd import sps
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "t.c"
+    src.write_text(C_PROGRAM)
+    exe = tmp_path / "t"
+    libdir = os.path.dirname(sps.LIB_PATH)
+    cmd = [gcc, "-std=c99", "-Wall", "-Werror=implicit-function-declaration", "-D__HIP_PLATFORM_AMD__",
+           "-I" + os.path.join(ROOT, "include"), "-I/opt/rocm/include", str(src), "-L" + libdir, "-lsps",
+           "-Wl,-rpath," + libdir, "-o", str(exe)]
+    subprocess.run(cmd, check=True, capture_output=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0, out
+    assert "domain" in out.stdout

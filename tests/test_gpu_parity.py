@@ -157,6 +157,17 @@ def test_invalid_arguments_are_rejected():
             m.Plan(*args)
 
 
+def test_read_only_attributes():
+    m = sps()
+    with m.Plan(3, 1000, 16, 128, 6.0) as p:
+        assert p.get(m.ATTR_NBLOCKS) == (1000 + 63) // 64
+        assert p.get(m.ATTR_NWIDTHS) == 5
+        assert p.get(m.ATTR_BLOCK_STRIDE) == m.BLOCK_STRIDE == 64
+        for attr in (m.ATTR_NBLOCKS, m.ATTR_NWIDTHS, m.ATTR_BLOCK_STRIDE):
+            with pytest.raises(m.SpsError):
+                p.set(attr, 32)
+
+
 def test_large_config_plain_equals_fused():
     # Full single-large-file workload: the per-stage path and the fused path
     # must produce identical candidate sets (every row, every width).
