@@ -397,6 +397,13 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
         if (S[q] > lo && !ab) ab = (double)S[q] / ((kMadToSigma * (double)mad) * sqw) > A.theta;
         in[q] = ab;
       }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        M[q] = ballot(in[q]);
+        best[q] = in[q] ? S[q] : INT_MIN;
+      }
+      // (the per-lane flags are consumed above: masking them under the
+      // branch below would make the compiler keep them as bytes in a VGPR)
       if (clean) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) V[q] = ~0ull;
@@ -404,13 +411,9 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           V[q] = lane_range(vlo - eg - 64 * q, vhi - eg - 64 * q);
-          in[q] = in[q] && ((V[q] >> lane) & 1ull);
+          M[q] &= V[q];
+          best[q] = ((V[q] >> lane) & 1ull) ? best[q] : INT_MIN;
         }
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        M[q] = ballot(in[q]);
-        best[q] = in[q] ? S[q] : INT_MIN;
       }
       wave_max4_u(best[0], best[1], best[2], best[3]);
 #pragma unroll

@@ -4,6 +4,8 @@
 // lanes of the wave active (wave-uniform control flow).
 #pragma once
 
+#include <climits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -57,23 +59,31 @@ __device__ __forceinline__ int wave_scan_incl(int v) {
   return v;
 }
 
+// One level of a max-reduction: max(v, v moved by CTRL). Masked-off rows
+// receive INT_MIN, the identity of max, which lets the compiler fold the lane
+// move into the max itself (one DPP instruction per level).
+template <int CTRL, int RM = 0xf>
+__device__ __forceinline__ int max_step(int v) {
+  return max(v, dpp<CTRL, RM>(INT_MIN, v));
+}
+
 // Maximum over the 64 lanes, returned wave-uniform.
 __device__ __forceinline__ int wave_max_u(int v) {
-  v = max(v, dpp<0xb1>(v, v));        // quad_perm [1,0,3,2]
-  v = max(v, dpp<0x4e>(v, v));        // quad_perm [2,3,0,1]
-  v = max(v, dpp<0x141>(v, v));       // row_half_mirror
-  v = max(v, dpp<0x140>(v, v));       // row_mirror
-  v = max(v, dpp<0x142, 0xa>(v, v));  // row_bcast:15
-  v = max(v, dpp<0x143, 0xc>(v, v));  // row_bcast:31
+  v = max_step<0xb1>(v);        // quad_perm [1,0,3,2]
+  v = max_step<0x4e>(v);        // quad_perm [2,3,0,1]
+  v = max_step<0x141>(v);       // row_half_mirror
+  v = max_step<0x140>(v);       // row_mirror
+  v = max_step<0x142, 0xa>(v);  // row_bcast:15
+  v = max_step<0x143, 0xc>(v);  // row_bcast:31
   return readlane(v, 63);
 }
 
 template <int CTRL, int RM>
 __device__ __forceinline__ void max_step4(int& a, int& b, int& c, int& d) {
-  a = max(a, dpp<CTRL, RM>(a, a));
-  b = max(b, dpp<CTRL, RM>(b, b));
-  c = max(c, dpp<CTRL, RM>(c, c));
-  d = max(d, dpp<CTRL, RM>(d, d));
+  a = max_step<CTRL, RM>(a);
+  b = max_step<CTRL, RM>(b);
+  c = max_step<CTRL, RM>(c);
+  d = max_step<CTRL, RM>(d);
 }
 
 // wave_max_u of four values at once, interleaved so that the DPP latencies
