@@ -162,7 +162,7 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
   const int nw = NW > 0 ? NW : A.nw;
   __shared__ uint32_t ring[kRing];
   __shared__ int32_t tlo[kMaxWidths][kGroups];
-  __shared__ int32_t thi[kMaxWidths][kGroups];
+  __shared__ int32_t thi[kMaxWidths][kGroups];  // S > thi: above for sure (INT_MAX: never)
   __shared__ int32_t tmad[kMaxWidths][kGroups];
   __shared__ uint4 gsum[kMaxWidths][kGroups];
   __shared__ RunSum carry[kMaxWidths];
@@ -268,7 +268,7 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
     if (tthr) {
       const Bound bd = make_bound(cur_mad, tsq, A.theta);
       tlo[tj][tg] = bd.lo;
-      thi[tj][tg] = bd.hi;
+      thi[tj][tg] = bd.hi == INT_MAX ? INT_MAX : bd.hi - 1;
       tmad[tj][tg] = cur_mad;
     }
     if (c + 1 < nsteps) next_mad = fetch_mad(c + 1);
@@ -282,11 +282,13 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
       cbuf_n[buf ^ 1] = 0u;
       if (fl_n) fl_base = atomicAdd(A.ncand, fl_n);
     }
+    uint32_t fullmask;  // widths whose 4 groups of this wave are full runs (summaries written)
     // interior step: every position of every width is valid, no masks needed
     const bool clean = cC - 64 >= max(A.maxw, max(e_lo0, e_lo1 + A.maxw)) &&
                        cC + kC - 1 <= min(e_seg, e_row - A.maxw);
     {
       uint32_t flagged = 0u;
+      fullmask = 0u;
       auto fast = [&](auto CLEAN) {
         // widths below 8: lane l reads window end l of each of the wave's 4 groups
         int cur_shift = -1;
@@ -350,7 +352,34 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
           // one comparison of the largest of the four (no short-circuit: a
           // logical or lets the compiler split the load and branch)
           const int dm = max(max(d0, d1), max(d2, d3));
-          flagged |= ballot(dm > T) ? (1u << j) : 0u;
+          const uint64_t hit = ballot(dm > T);
+          flagged |= hit ? (1u << j) : 0u;
+          if (CLEAN && hit == ~0ull) {
+            // Every lane has a candidate: if every one of the wave's 256
+            // positions is above for sure, its 4 groups are single full runs
+            // and their summaries are written here (the run pass skips them).
+            const int F = thi[j][4 * wave + gq];
+            if (ballot(min(min(d0, d1), min(d2, d3)) > F) == ~0ull) {
+              int rm = dm;  // group maximum, in every lane of the row
+              rm = max_step<0xb1>(rm);
+              rm = max_step<0x4e>(rm);
+              rm = max_step<0x141>(rm);
+              rm = max_step<0x140>(rm);
+              // first position of the maximum within the group (0..63)
+              const int kk = d0 == rm ? 0 : (d1 == rm ? 1 : (d2 == rm ? 2 : 3));
+              int pos = dm == rm ? 4 * (lane & 15) + kk : 64;
+              pos = min_step<0xb1>(pos);
+              pos = min_step<0x4e>(pos);
+              pos = min_step<0x141>(pos);
+              pos = min_step<0x140>(pos);
+              if ((lane & 15) == 0) {
+                const int g = 4 * wave + gq;
+                gsum[j][g] = make_uint4((uint32_t)(kNonEmpty | kFull | kHead) | ((uint32_t)pos << 8), (uint32_t)rm,
+                                        0u, (uint32_t)tmad[j][g]);
+              }
+              fullmask |= 1u << j;
+            }
+          }
         }
       };
       if (clean) fast(std::true_type{});
@@ -371,8 +400,9 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
         if (base + i < A.cap) A.cands[base + i] = cbuf[buf ^ 1][i];
     }
     const uint32_t smask = step_mask;
+    const uint32_t rmask = smask & ~fullmask;
     for (int j = 0; j < nw; ++j) {
-      if (!((smask >> j) & 1u)) continue;
+      if (!((rmask >> j) & 1u)) continue;
       const int w = 1 << j, sh = group_shift(w);
       const int eg = cC - sh + 256 * wave;
       const int vhi = min(e_seg + w - 1, e_row);
@@ -381,7 +411,7 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
       const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, lane == 0,
                        A.sample_offset};
       const int4 LO = *reinterpret_cast<const int4*>(&tlo[j][4 * wave]);
-      const int4 HI = *reinterpret_cast<const int4*>(&thi[j][4 * wave]);
+      const int4 HI = *reinterpret_cast<const int4*>(&thi[j][4 * wave]);  // S > HI: above for sure
       const int4 MD = *reinterpret_cast<const int4*>(&tmad[j][4 * wave]);
       int S[4], best[4];
       bool in[4];
@@ -393,7 +423,7 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
         const int lo = q == 0 ? LO.x : q == 1 ? LO.y : q == 2 ? LO.z : LO.w;
         const int hi = q == 0 ? HI.x : q == 1 ? HI.y : q == 2 ? HI.z : HI.w;
         const int mad = q == 0 ? MD.x : q == 1 ? MD.y : q == 2 ? MD.z : MD.w;
-        bool ab = S[q] >= hi && hi != INT_MAX;
+        bool ab = S[q] > hi;
         if (S[q] > lo && !ab) ab = (double)S[q] / ((kMadToSigma * (double)mad) * sqw) > A.theta;
         in[q] = ab;
       }

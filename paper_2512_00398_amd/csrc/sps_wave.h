@@ -67,6 +67,11 @@ __device__ __forceinline__ int max_step(int v) {
   return max(v, dpp<CTRL, RM>(INT_MIN, v));
 }
 
+template <int CTRL, int RM = 0xf>
+__device__ __forceinline__ int min_step(int v) {
+  return min(v, dpp<CTRL, RM>(INT_MAX, v));
+}
+
 // Maximum over the 64 lanes, returned wave-uniform.
 __device__ __forceinline__ int wave_max_u(int v) {
   v = max_step<0xb1>(v);        // quad_perm [1,0,3,2]
