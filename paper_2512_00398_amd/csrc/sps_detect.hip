@@ -80,31 +80,6 @@ __device__ __forceinline__ uint4 group_pack(uint64_t M, uint64_t V, int S, int m
   return make_uint4(flags | ((uint32_t)hl << 8) | ((uint32_t)tl << 16), (uint32_t)hS, (uint32_t)tS, (uint32_t)mad);
 }
 
-// One level of the in-order combine of 16 group summaries held by the lanes
-// of a DPP row: lanes at multiples of 2D absorb the summary of lane + D; the
-// run closed at the junction (if any) is returned in `pe`.
-template <int D>
-__device__ __forceinline__ RunSum rs_absorb(const RunSum& g, int k, bool act, Pending& pe) {
-  RunSum r;
-  r.flags = row_down<D>(0, g.flags);
-  r.hi = row_down<D>(0, g.hi);
-  r.ti = row_down<D>(0, g.ti);
-  r.pad = 0;
-  r.hq = row_down<D>(0.0, g.hq);
-  r.tq = row_down<D>(0.0, g.tq);
-  const bool mine = (k & (2 * D - 1)) == 0;
-  const RunSum c = rs_combine_p(g, r, pe);
-  pe.f = pe.f && act && mine;
-  RunSum o;
-  o.flags = mine ? c.flags : g.flags;
-  o.hi = mine ? c.hi : g.hi;
-  o.ti = mine ? c.ti : g.ti;
-  o.pad = 0;
-  o.hq = mine ? c.hq : g.hq;
-  o.tq = mine ? c.tq : g.tq;
-  return o;
-}
-
 // Number of lanes below this one in mask m.
 __device__ __forceinline__ int lane_prefix(uint64_t m) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -136,6 +111,87 @@ __device__ __forceinline__ void emit_batch(const Pending (&p)[NP], const Emitter
       else emit_global(E, c);
     }
   }
+}
+
+// One level of the segmented max-scan in step_fold: unless a run starts in
+// the lanes this one already covers, take the best of the lanes D further
+// back (earlier positions win ties).
+template <int D>
+__device__ __forceinline__ void scan_level(double& q, int& qi, int& s, int& fs) {
+  const double pq = row_up<D>(0.0, q);
+  const int pi = row_up<D>(0, qi), ps = row_up<D>(1, s), pfs = row_up<D>(0, fs);
+  const bool take = !s && !(q > pq);
+  q = take ? pq : q;
+  qi = take ? pi : qi;
+  fs = s ? fs : pfs;
+  s |= ps;
+}
+
+// Combines the 16 group summaries held by each row of 16 lanes (lane k =
+// group k, in window-end order; at most the leading and trailing groups of a
+// row are empty) into the row's summary, and returns in pe[0], pe[1] the runs
+// that close inside the row without touching its ends. On return lane 0 of
+// each row holds the row summary in (fl, hi, hq, ti, tq).
+//
+// A group contributes up to two pieces of runs: its head piece (the run at
+// its start, or the whole group when full) and its tail piece. The tail piece
+// of group k-1 (or the whole group when full) joins the head piece of group k
+// when both are above at the junction. The best of the run leaving each group
+// at its end is a segmented max-scan over the groups (a new segment wherever
+// the group is not full or does not join the one before), carrying whether
+// that run began at the row start.
+__device__ __forceinline__ void step_fold(int& fl, int& hi, double& hq, int& ti, double& tq, int k, Pending (&pe)[3]) {
+  const bool ne = fl & kNonEmpty, F = fl & kFull, H = fl & kHead, T = fl & kTail;
+  const bool eo = F || T;  // above at the group end
+  // (lane exchanges run in every lane: never on the right of && or ||, which
+  // would run them only where the left side holds)
+  const int eo_prev = row_up<1>(0, (int)eo);
+  const int ne_prev = row_up<1>(0, (int)ne), ne_next = row_down<1>(0, (int)ne);
+  const bool C = H & (eo_prev != 0);                // joins the run of group k-1
+  const bool Cn = row_down<1>(0, (int)C) != 0;      // group k+1 joins this one
+  const bool first = ne & (ne_prev == 0);
+  const bool last = ne & (ne_next == 0);
+  // run leaving each group: best (q at qi) and whether it began at the row start
+  double q = F ? hq : tq;
+  int qi = F ? hi : ti;
+  int s = !(F && C);
+  int fs = first && F;
+  scan_level<1>(q, qi, s, fs);
+  scan_level<2>(q, qi, s, fs);
+  scan_level<4>(q, qi, s, fs);
+  scan_level<8>(q, qi, s, fs);
+  // head piece of a group that is not full: the run closes inside the group
+  const double oq = row_up<1>(0.0, q);
+  const int oi = row_up<1>(0, qi), ofs = row_up<1>(0, fs);
+  const bool r1 = H && !F;
+  const bool join = C && !(hq > oq);
+  const double r1q = join ? oq : hq;
+  const int r1i = join ? oi : hi;
+  const bool r1fs = C ? ofs != 0 : first;
+  // run leaving the group: closes at its end unless group k+1 joins it
+  const bool r2 = eo && !Cn;
+  pe[0].f = r1 && !r1fs;
+  pe[0].i = r1i;
+  pe[0].q = r1q;
+  pe[1].f = r2 && !last && !fs;
+  pe[1].i = qi;
+  pe[1].q = q;
+  // the run from the row start ends in exactly one lane (if the first group
+  // starts above); the run reaching the row end leaves the last group
+  const bool hl = (r1 && r1fs) || (r2 && fs);
+  const int hsrc = max(row_max(hl ? (int)lane_id() : -1), 0);
+  const int tsrc = max(row_max(last ? (int)lane_id() : -1), 0);
+  const double hv_q = (r1 && r1fs) ? r1q : q;
+  const int hv_i = (r1 && r1fs) ? r1i : qi;
+  const double rhq = lane_read(hv_q, hsrc), rtq = lane_read(q, tsrc);
+  const int rhi = lane_read(hv_i, hsrc), rti = lane_read(qi, tsrc);
+  const int bits = row_or((ne ? 1 : 0) | ((ne && !F) ? 2 : 0) | ((first && H) ? 4 : 0) | ((last && eo) ? 8 : 0));
+  const bool rne = bits & 1, full = rne && !(bits & 2);
+  fl = !rne ? 0 : (kNonEmpty | (full ? (kFull | kHead) : (((bits & 4) ? kHead : 0) | ((bits & 8) ? kTail : 0))));
+  hi = rhi;
+  hq = rhq;
+  ti = rti;
+  tq = rtq;
 }
 
 // Window ends of width w in a step start (64 - ceil(w/2) mod 64) mod 64
@@ -475,32 +531,34 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
         const int j = act ? jb : 0;
         const int w = 1 << j, sh = group_shift(w);
         const uint4 pk = gsum[j][k];
-        RunSum gs = rs_empty();
+        int fl = 0, hi = 0, ti = 0;
+        double hq = 0.0, tq = 0.0;
         if (act) {
           const double den = (kMadToSigma * (double)(int)pk.w) * s_sqw[j];
           const int i0 = s0 + cC - sh + 64 * k - w;
-          gs.flags = (int)(pk.x & 15u);
-          gs.hi = i0 + (int)((pk.x >> 8) & 63u);
-          gs.ti = i0 + (int)((pk.x >> 16) & 63u);
-          gs.hq = (double)(int)pk.y / den;
-          gs.tq = (double)(int)pk.z / den;
+          fl = (int)(pk.x & 15u);
+          hi = i0 + (int)((pk.x >> 8) & 63u);
+          ti = i0 + (int)((pk.x >> 16) & 63u);
+          hq = (double)(int)pk.y / den;
+          tq = (double)(int)pk.z / den;
         }
         const Emitter em{cbuf[buf], &cbuf_n[buf], A.cands, A.ncand, A.cap, dm, (uint32_t)w, true,
                          A.sample_offset};
-        Pending pe[1];
-        gs = rs_absorb<1>(gs, k, act, pe[0]);
-        emit_batch(pe, em, lane);
-        gs = rs_absorb<2>(gs, k, act, pe[0]);
-        emit_batch(pe, em, lane);
-        gs = rs_absorb<4>(gs, k, act, pe[0]);
-        emit_batch(pe, em, lane);
-        gs = rs_absorb<8>(gs, k, act, pe[0]);
-        emit_batch(pe, em, lane);
+        Pending pe[3];
+        step_fold(fl, hi, hq, ti, tq, k, pe);
+        // the row's step summary, folded into the width's carried run by lane 0 of the row
         const bool owner = act && k == 0;
         RunSum cj = rs_empty();
         if (owner) cj = carry[j];
-        cj = rs_combine_p(cj, gs, pe[0]);
-        pe[0].f = pe[0].f && owner;
+        RunSum st;
+        st.flags = fl;
+        st.hi = hi;
+        st.ti = ti;
+        st.pad = 0;
+        st.hq = hq;
+        st.tq = tq;
+        cj = rs_combine_p(cj, st, pe[2]);
+        pe[2].f = pe[2].f && owner;
         if (owner) carry[j] = cj;
         emit_batch(pe, em, lane);
       }

@@ -144,4 +144,47 @@ __device__ __forceinline__ double row_down(double old, double v) {
   return __longlong_as_double(((long long)hi << 32) | (uint32_t)lo);
 }
 
+// Value of lane i - D of the same row of 16 lanes (DPP row_shr:D); lanes
+// whose source lies before the row start receive `old`.
+template <int D>
+__device__ __forceinline__ int row_up(int old, int v) {
+  static_assert(D >= 1 && D <= 15, "row_shr range");
+  return dpp<0x110 + D>(old, v);
+}
+
+template <int D>
+__device__ __forceinline__ double row_up(double old, double v) {
+  const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+  const int lo = row_up<D>((int)(uint32_t)o, (int)(uint32_t)x);
+  const int hi = row_up<D>((int)(o >> 32), (int)(x >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (uint32_t)lo);
+}
+
+// Bitwise or over each row of 16 lanes, in every lane of the row.
+__device__ __forceinline__ int row_or(int v) {
+  v |= dpp<0xb1>(0, v);   // quad_perm [1,0,3,2]
+  v |= dpp<0x4e>(0, v);   // quad_perm [2,3,0,1]
+  v |= dpp<0x141>(0, v);  // row_half_mirror
+  v |= dpp<0x140>(0, v);  // row_mirror
+  return v;
+}
+
+// Maximum over each row of 16 lanes, in every lane of the row.
+__device__ __forceinline__ int row_max(int v) {
+  v = max_step<0xb1>(v);
+  v = max_step<0x4e>(v);
+  v = max_step<0x141>(v);
+  v = max_step<0x140>(v);
+  return v;
+}
+
+// Value of v in lane l (per-lane l, 0..63).
+__device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn_ds_bpermute(l << 2, v); }
+
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = lane_read((int)(uint32_t)x, l), hi = lane_read((int)(x >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (uint32_t)lo);
+}
+
 }  // namespace sps
