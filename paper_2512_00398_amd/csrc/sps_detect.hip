@@ -224,7 +224,7 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
   __shared__ RunSum carry[kMaxWidths];
   __shared__ double s_sqw[kMaxWidths];
   __shared__ sps_cand cbuf[2][kCbuf];
-  __shared__ uint32_t wtot[2][4];
+  __shared__ __align__(16) uint32_t wtot[2][4];
   __shared__ uint32_t step_mask, flush_n, flush_base;
   __shared__ uint32_t cbuf_n[2];
 
@@ -246,10 +246,10 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
                    (!VIRT || ((reinterpret_cast<uintptr_t>(hr) & 15u) == 0));
   const int tmin = A.tmin ? *A.tmin : 0;
   const uint32_t dm = (uint32_t)row + A.row_offset;
-  const int e_row = N - s0;  // E <= N - s0      <=> i <= N - w
-  const int e_seg = s1 - s0; // E < s1 - s0 + w  <=> i < s1
+  const int e_row0 = readfirst(N - s0);  // E <= N - s0      <=> i <= N - w
+  const int e_seg0 = readfirst(s1 - s0); // E < s1 - s0 + w  <=> i < s1
   // E >= e_lo0 and E >= tmin - s0 + w: window ends after e_first, starts at or after tmin
-  const int e_lo0 = A.e_first - s0, e_lo1 = tmin - s0;
+  const int e_lo00 = readfirst(A.e_first - s0), e_lo10 = readfirst(tmin - s0);
 
   // bound-table thread: (width tj, group tg)
   const bool tthr = tid < nw * kGroups;
@@ -310,11 +310,16 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
   for (int c = 0; c < nsteps; ++c) {
     const int cC = c * kC;
     const int buf = c & 1;
+    // The valid-range limits, opaque per step: otherwise the compiler hoists
+    // every per-width limit derived from them out of the loop, and the
+    // scalar registers they take are spilled and reloaded in every step.
+    int e_row = e_row0, e_seg = e_seg0, e_lo0 = e_lo00, e_lo1 = e_lo10;
+    asm volatile("" : "+s"(e_row), "+s"(e_seg), "+s"(e_lo0), "+s"(e_lo1));
     // ---- A: ring and bounds of step c
     {
-      uint32_t woff = 0;
-      for (int v = 0; v < wave; ++v) woff += wtot[buf][v];
-      const uint32_t tot = wtot[buf][0] + wtot[buf][1] + wtot[buf][2] + wtot[buf][3];
+      const uint4 wt = *reinterpret_cast<const uint4*>(&wtot[buf][0]);
+      const uint32_t woff = (wave > 0 ? wt.x : 0u) + (wave > 1 ? wt.y : 0u) + (wave > 2 ? wt.z : 0u);
+      const uint32_t tot = wt.x + wt.y + wt.z + wt.w;
       // P[E] = sum of r over the segment's first E samples; thread tid owns
       // E = cC + 4*tid + q, so every 64 consecutive E of a wave row are one group
       const uint32_t pb = carryP + woff + incl - p3;
