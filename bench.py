@@ -38,8 +38,8 @@ KERNEL_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md
-    "detect": ("570d9626b8c1943b", (2237852 * 2 + 169947) * 1024),
-    "block_stats": ("4f19ddfb9384fc69", (4325085 * 2 + 146951) * 1024),
+    "detect": ("1cb0e01902098699", (2237806 * 2 + 170094) * 1024),
+    "block_stats": ("5132f1f8ce44a7f3", (4325127 * 2 + 146895) * 1024),
 }
 
 
