@@ -35,7 +35,7 @@ struct RowRef {
   const float* h;
   int Hx;
   __device__ __forceinline__ float at(int t) const {
-    if (VIRT) return t < Hx ? h[t] : g[t - Hx];
+    if (VIRT) return *(t < Hx ? h + t : g + (t - Hx));  // one load from the selected address
     return g[t];
   }
   __device__ __forceinline__ int iat(int t) const { return (int)at(t); }
@@ -394,12 +394,17 @@ __device__ __forceinline__ void stats_chain(const StatsArgs& a, const int chain,
     if (lane == 0) { med[kb0] = c.m; mad[kb0] = c.d; }
   }
 
-  // Samples entering / leaving the window at block kk, prefetched 4 blocks ahead.
+  // Samples entering / leaving the window at block kk, prefetched 4 blocks
+  // ahead. Every lane loads (from a clamped in-row position) and unused lanes
+  // are zeroed afterwards: loads skipped under a branch would leave the
+  // compiler unsure how many are in flight, and it would then wait for all of
+  // them, the prefetch included, before each block.
   auto fetch = [&](int kk, float& va, float& vb) {
     const int ep = min(kk * kStride, N), e = min(kk * kStride + kStride, N);
     const int lp = max(t0, ep - L), l2 = max(t0, e - L);
-    va = (lane < e - ep) ? c.row.at(ep + lane) : 0.f;
-    vb = (lane < l2 - lp) ? c.row.at(lp + lane) : 0.f;
+    const float ra = c.row.at(min(ep + lane, N - 1)), rb = c.row.at(min(lp + lane, N - 1));
+    va = (lane < e - ep) ? ra : 0.f;
+    vb = (lane < l2 - lp) ? rb : 0.f;
   };
   float pa[4], pb[4];
 #pragma unroll
@@ -415,7 +420,9 @@ __device__ __forceinline__ void stats_chain(const StatsArgs& a, const int chain,
         const int ep = min(kk * kStride, N), e = min(kk * kStride + kStride, N);
         const int lp = max(t0, ep - L), l2 = max(t0, e - L);
         chain_step(c, l2, e, lane < e - ep, (int)va, lane < l2 - lp, (int)vb);
-        if (lane == 0) { med[kk] = c.m; mad[kk] = c.d; }
+        // every lane stores the same (wave-uniform) values: no branch around the stores
+        med[kk] = c.m;
+        mad[kk] = c.d;
       }
     }
   }
