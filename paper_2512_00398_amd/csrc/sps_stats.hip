@@ -431,9 +431,9 @@ __device__ __forceinline__ void stats_chain(const StatsArgs& a, const int chain,
 template <int NB, int WPG, bool VIRT>
 __global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
   __shared__ uint32_t hist[WPG][NB / 2];
-  // wave index kept in a VGPR: the chain state then stays on the vector unit,
-  // which measures faster than moving its bookkeeping to the shared scalar unit
-  const int wave = threadIdx.x >> 6;
+  // wave index made uniform: the chain's bookkeeping then runs on the scalar
+  // unit beside the vector work of the other waves
+  const int wave = readfirst(threadIdx.x >> 6);
   const int chain = blockIdx.x * WPG + wave;
   if (chain >= a.nchains) return;  // whole wave leaves; no block barriers are used
   stats_chain<NB, VIRT>(a, chain, hist[wave], lane_id());
