@@ -18,11 +18,13 @@
 // For width w the step's positions are grouped 64 per (wave, q) so that each
 // group shares one centre block k* (window ends E with E - ceil(w/2) = 0 mod
 // 64): the group's bound is one scalar. Fast pass: per lane and width two LDS
-// reads, a subtract and a compare folded into a ballot. Widths with any
+// reads, a subtract and a compare folded into a ballot; groups whose every
+// position is above for sure are summarised there. Widths with any other
 // position beyond the bound take the run pass: per group a DPP max-reduction
-// and a packed summary in LDS, then DPP row trees over the 16 groups of each
-// flagged width, folded into the carried run summaries that stitch runs
-// across steps and, through the fix-up kernel, segments.
+// and a packed summary in LDS, then a segmented max-scan over the 16 groups
+// of each flagged width in one DPP row, folded into the carried run
+// summaries that stitch runs across steps and, through the fix-up kernel,
+// segments.
 // Candidates are staged in LDS and flushed with one global atomic per step.
 #include <climits>
 #include <type_traits>
@@ -204,14 +206,16 @@ __device__ __forceinline__ int group_shift(int w) {
 // NW > 0: the number of widths is a compile-time constant (fast pass unrolled);
 // NW == 0: any number of widths.
 //
-// Step c has three phases separated by barriers:
+// Step c has four phases separated by three barriers:
 //   A  write P of step c into the ring; bounds for step c's centre blocks
-//   B  fast pass over step c; residuals and wave scan of step c+1; flush slot
-//      for the candidates staged during step c-1
-//   C  copy those candidates out; run pass over step c's flagged widths:
-//      one packed summary per (width, 64-position group) into LDS
-//   D  DPP row trees combine each flagged width's 16 group summaries and
-//      fold them into the width's carried run (no barrier before the next A)
+//   B  fast pass over step c (summaries of groups above for sure); residuals
+//      and wave scan of step c+1; flush slot for the candidates staged
+//      during step c-1
+//   C  copy those candidates out; run pass over step c's other flagged
+//      groups: one packed summary per (width, 64-position group) into LDS
+//   D  each flagged width's 16 group summaries are combined by a segmented
+//      scan in one row of 16 lanes and folded into the width's carried run
+//      (no barrier before the next A)
 // Samples, medians and MADs are fetched one step ahead of their use.
 template <int NW, bool VIRT>
 __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task) {
@@ -519,9 +523,9 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
     __syncthreads();  // BC
 
     // ---- D: the 16 group summaries of each flagged width are combined in
-    // order by a DPP row tree (one row of 16 lanes per width, four widths per
-    // wave; the wave that takes the first four rotates with the step), then
-    // folded into the width's carried run. Unflagged widths only close a run.
+    // one row of 16 lanes (four widths per wave; the wave that takes the
+    // first four rotates with the step), then folded into the width's carried
+    // run. Unflagged widths only close a run.
     {
       const int nflag = __popc(smask);
       const int r = lane >> 4, k = lane & 15;
