@@ -48,40 +48,6 @@ __device__ __forceinline__ void run_best(uint64_t run, int S, int lane, int& bes
   bestLane = ctz(ballot(in && S == bestS));
 }
 
-// A 64-position group's run summary, packed for LDS: x = flags | head best
-// lane << 8 | tail best lane << 16, y = head S, z = tail S, w = MAD of the
-// group's centre block (the group's S/N denominator is K * MAD * sqrt(w)).
-// M: above lanes, V: valid lanes (contiguous). Runs touching neither end of
-// the valid lanes are emitted here; `full_best`/`full_lane` is the best of
-// all valid lanes (used when every valid lane is above).
-__device__ __forceinline__ uint4 group_pack(uint64_t M, uint64_t V, int S, int mad, double den, int i0, int lane,
-                                            int full_best, const Emitter& E) {
-  if (!V) return make_uint4(0u, 0u, 0u, (uint32_t)mad);
-  if (!M) return make_uint4((uint32_t)kNonEmpty, 0u, 0u, (uint32_t)mad);
-  if (M == V) {
-    const int bl = ctz(ballot(((V >> lane) & 1ull) && S == full_best));
-    return make_uint4((uint32_t)(kNonEmpty | kFull | kHead) | ((uint32_t)bl << 8), (uint32_t)full_best, 0u,
-                      (uint32_t)mad);
-  }
-  uint32_t flags = kNonEmpty;
-  int hl = 0, tl = 0, hS = 0, tS = 0;
-  const int fv = ctz(V), lv = msb(V);
-  uint64_t m = M;
-  while (m) {
-    const int a = ctz(m);
-    const uint64_t gap = ~m & (~0ull << a);
-    const int b = gap ? ctz(gap) : 64;
-    const uint64_t run = (b == 64 ? ~0ull : ((1ull << b) - 1ull)) & (~0ull << a);
-    int bs, bl;
-    run_best(run, S, lane, bs, bl);
-    if (a == fv) { flags |= kHead; hl = bl; hS = bs; }
-    else if (b - 1 == lv) { flags |= kTail; tl = bl; tS = bs; }
-    else emit(E, i0 + bl, (double)bs / den);
-    m &= ~run;
-  }
-  return make_uint4(flags | ((uint32_t)hl << 8) | ((uint32_t)tl << 16), (uint32_t)hS, (uint32_t)tS, (uint32_t)mad);
-}
-
 // Number of lanes below this one in mask m.
 __device__ __forceinline__ int lane_prefix(uint64_t m) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -114,6 +80,56 @@ __device__ __forceinline__ void emit_batch(const Pending (&p)[NP], const Emitter
     }
   }
 }
+
+// A 64-position group's run summary, packed for LDS: x = flags | head best
+// lane << 8 | tail best lane << 16, y = head S, z = tail S, w = MAD of the
+// group's centre block (the group's S/N denominator is K * MAD * sqrt(w)).
+// M: above lanes, V: valid lanes (contiguous). Runs touching neither end of
+// the valid lanes are emitted here; `full_best`/`full_lane` is the best of
+// all valid lanes (used when every valid lane is above).
+__device__ __forceinline__ uint4 group_pack(uint64_t M, uint64_t V, int S, int mad, double den, int i0, int lane,
+                                            int full_best, const Emitter& E) {
+  if (!V) return make_uint4(0u, 0u, 0u, (uint32_t)mad);
+  if (!M) return make_uint4((uint32_t)kNonEmpty, 0u, 0u, (uint32_t)mad);
+  if (M == V) {
+    const int bl = ctz(ballot(((V >> lane) & 1ull) && S == full_best));
+    return make_uint4((uint32_t)(kNonEmpty | kFull | kHead) | ((uint32_t)bl << 8), (uint32_t)full_best, 0u,
+                      (uint32_t)mad);
+  }
+  uint32_t flags = kNonEmpty;
+  int hl = 0, tl = 0, hS = 0, tS = 0;
+  const int fv = ctz(V), lv = msb(V);
+  // runs touching neither end: lane k collects the k-th one (at most 32),
+  // divided and written together after the loop
+  int pi = 0, pS = 0, np = 0;
+  uint64_t m = M;
+  while (m) {
+    const int a = ctz(m);
+    const uint64_t gap = ~m & (~0ull << a);
+    const int b = gap ? ctz(gap) : 64;
+    const uint64_t run = (b == 64 ? ~0ull : ((1ull << b) - 1ull)) & (~0ull << a);
+    int bs, bl;
+    run_best(run, S, lane, bs, bl);
+    if (a == fv) { flags |= kHead; hl = bl; hS = bs; }
+    else if (b - 1 == lv) { flags |= kTail; tl = bl; tS = bs; }
+    else {
+      const bool mine = lane == np;
+      pi = mine ? i0 + bl : pi;
+      pS = mine ? bs : pS;
+      ++np;
+    }
+    m &= ~run;
+  }
+  if (np) {
+    Pending p[1];
+    p[0].f = lane < np;
+    p[0].i = pi;
+    p[0].q = (double)pS / den;
+    emit_batch(p, E, lane);
+  }
+  return make_uint4(flags | ((uint32_t)hl << 8) | ((uint32_t)tl << 16), (uint32_t)hS, (uint32_t)tS, (uint32_t)mad);
+}
+
 
 // One level of the segmented max-scan in step_fold: unless a run starts in
 // the lanes this one already covers, take the best of the lanes D further
