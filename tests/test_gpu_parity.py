@@ -291,3 +291,25 @@ def test_noise_only_false_alarm_rate_on_gpu():
         z = (cnt - lam) / math.sqrt(lam)
         print("theta %.1f: %d candidates, expected %.1f, z = %.2f" % (th, cnt, lam, z), flush=True)
         assert abs(z) < 4.0, (th, cnt, lam, z)
+
+
+def test_long_runs_full_groups_across_steps_and_segments():
+    # A strong slow sinusoid (period 16384, amplitude 12 sigma) under a short
+    # baseline window: the widest boxcars stay above the threshold for
+    # thousands of samples, so whole 64-position groups and whole 1024-sample
+    # steps are above (summarised in the fast pass), runs cross step and
+    # segment boundaries (folded and fixed up), and narrow widths cross the
+    # threshold often near the run edges. Segment lengths 16384 and 32768
+    # move the segment boundaries through the runs.
+    rng = np.random.default_rng(1234)
+    n = 1 << 16
+    t = np.arange(n)
+    rows = []
+    for r in range(4):
+        noise = np.round(rng.normal(0.0, 64.0, n))
+        wave = np.round(768.0 * np.sin(2 * np.pi * (t + 2048 * r) / 16384.0))
+        rows.append(32768.0 + noise + wave)
+    x = np.stack(rows).astype(np.float32)
+    for seg in (0, 16384, 32768):
+        got, ref, _ = check(x, 4096, 2048, 6.0, "long runs seg=%d" % seg, detect_seg=seg)
+        assert ref.shape[0] > 100
