@@ -38,8 +38,8 @@ KERNEL_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md
-    "detect": ("1cb0e01902098699", (2237806 * 2 + 170094) * 1024),
-    "block_stats": ("5132f1f8ce44a7f3", (4325127 * 2 + 146895) * 1024),
+    "detect": ("21c57382d114e7b2", (2237764 * 2 + 170181) * 1024),
+    "block_stats": ("f3bc12ecb23ceb76", (4326792 * 2 + 141798) * 1024),
 }
 
 
