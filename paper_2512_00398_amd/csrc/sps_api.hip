@@ -78,6 +78,27 @@ int stats_seg_for(const sps_plan* p, int64_t nb) {
 
 int auto_stats_seg(const sps_plan* p) { return stats_seg_for(p, p->nblocks); }
 
+// Chain segments of rows whose first windows are clipped at the row start
+// (they grow from 64 samples to the full window): there the median and MAD
+// move far from block to block and the chain takes the slow queries, so the
+// row's first chain is made shorter by four window lengths in blocks (at most
+// half a segment) and the others longer (automatic segmentation only; the
+// measured optimum under drifting baselines). Fills seg (blocks of segments
+// 1, 2, ...), head (blocks of segment 0) and nseg.
+void stats_segments_clipped(const sps_plan* p, int64_t nb, int32_t& seg, int32_t& head, int32_t& nseg) {
+  seg = stats_seg_for(p, nb);
+  nseg = (int32_t)((nb + seg - 1) / seg);
+  head = seg;
+  if (p->stats_seg > 0 || nseg < 2) return;
+  const int64_t shift = std::min<int64_t>(4 * std::min<int64_t>(p->baseline_len, p->nsamp) / sps::kStride, seg / 2);
+  const int64_t seg2 = (nb + shift + nseg - 1) / nseg;
+  const int64_t h = nb - (int64_t)(nseg - 1) * seg2;
+  if (h >= 1 && h <= seg2) {
+    seg = (int32_t)seg2;
+    head = (int32_t)h;
+  }
+}
+
 // Positions per detection segment for rows of `npos` positions (tuning only).
 int detect_seg_for(const sps_plan* p, int64_t npos) {
   int64_t seg = p->detect_seg;
@@ -370,8 +391,7 @@ static int launch_stats(sps_plan* p, const float* d_series, hipStream_t stream, 
   a.L = p->baseline_len;
   a.nblocks = p->nblocks;
   a.kb_first = 0;
-  a.seg_blocks = auto_stats_seg(p);
-  a.nseg = (p->nblocks + a.seg_blocks - 1) / a.seg_blocks;
+  stats_segments_clipped(p, p->nblocks, a.seg_blocks, a.head_blocks, a.nseg);
   a.nchains = p->ndm * a.nseg;
   a.tmin = nullptr;
   a.med = d_median;
@@ -700,6 +720,7 @@ int stream_enqueue(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_c
   a.nblocks = s->nbv;
   a.kb_first = s->Hb;
   a.seg_blocks = stats_seg_for(p, s->nbv - s->Hb);
+  a.head_blocks = a.seg_blocks;
   a.nseg = (s->nbv - s->Hb + a.seg_blocks - 1) / a.seg_blocks;
   a.nchains = p->ndm * a.nseg;
   a.tmin = s->tmin;
@@ -1178,6 +1199,7 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
     a.nblocks = s.nblocks;
     a.kb_first = 0;
     a.seg_blocks = s.stats_seg;
+    a.head_blocks = s.stats_seg;
     a.nseg = s.stats_nseg;
     a.nchains = it.ndm * s.stats_nseg;
     a.tmin = nullptr;

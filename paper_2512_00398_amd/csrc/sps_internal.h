@@ -48,7 +48,8 @@ struct StatsArgs {
   int32_t N, L;        // virtual row length, baseline window
   int32_t nblocks;     // ceil(N / 64): row stride of med / mad
   int32_t kb_first;    // first block computed (blocks below it are carried in)
-  int32_t seg_blocks;  // blocks per chain segment
+  int32_t seg_blocks;  // blocks per chain segment (segments 1, 2, ...)
+  int32_t head_blocks; // blocks of segment 0 (<= seg_blocks)
   int32_t nseg;        // segments per row
   int32_t nchains;     // rows * nseg
   const int32_t* tmin; // device: no window reaches below *tmin (null: 0)

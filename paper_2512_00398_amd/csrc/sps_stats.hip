@@ -308,12 +308,16 @@ __device__ int sample_median(const RowRef<VIRT>& row, int lo, int hi, int lane) 
   return (int)(p ^ 0x80000000u);
 }
 
+// span_hi >= hi: the samples that centre the histogram are spread over
+// [lo, span_hi) (the windows this chain will see, when the first is clipped).
 template <int NB, bool VIRT>
-__device__ void chain_init(Chain<NB, VIRT>& c, int lo, int hi) {
+__device__ void chain_init(Chain<NB, VIRT>& c, int lo, int hi, int span_hi) {
   // Centre the first histogram on the median of samples spread over the
   // whole window (a contiguous run of samples can sit far from it when the
-  // data drift).
-  const int g = sample_median(c.row, lo, hi, c.lane);
+  // data drift); for a window clipped at the row start, over the samples the
+  // growing windows will take in, so that it need not be recentred (and the
+  // window recounted) as they grow.
+  const int g = sample_median(c.row, lo, span_hi, c.lane);
   const int below = rebuild(c, lo, hi, g - NB / 2);
   if (!full_query(c, below)) exact_block(c, lo, hi);
 }
@@ -373,8 +377,9 @@ template <int NB, bool VIRT>
 __device__ __forceinline__ void stats_chain(const StatsArgs& a, const int chain, uint32_t* H, const int lane) {
   const int row = chain / a.nseg;
   const int seg = chain - row * a.nseg;
-  const int kb0 = a.kb_first + seg * a.seg_blocks;
-  const int kb1 = min(a.nblocks, kb0 + a.seg_blocks);
+  // segment 0 has head_blocks blocks, the others seg_blocks each
+  const int kb0 = a.kb_first + (seg == 0 ? 0 : a.head_blocks + (seg - 1) * a.seg_blocks);
+  const int kb1 = min(a.nblocks, seg == 0 ? a.kb_first + a.head_blocks : kb0 + a.seg_blocks);
   const int N = a.N, L = a.L;
   const int t0 = a.tmin ? *a.tmin : 0;
   Chain<NB, VIRT> c;
@@ -390,7 +395,7 @@ __device__ __forceinline__ void stats_chain(const StatsArgs& a, const int chain,
   {
     const int e = min(kb0 * kStride + kStride, N), lo = max(t0, e - L);
     c.n = e - lo;
-    chain_init(c, lo, e);
+    chain_init(c, lo, e, min(N, max(e, lo + L)));
     if (lane == 0) { med[kb0] = c.m; mad[kb0] = c.d; }
   }
 
