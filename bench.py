@@ -38,8 +38,8 @@ KERNEL_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md
-    "detect": ("21c57382d114e7b2", (2237764 * 2 + 170181) * 1024),
-    "block_stats": ("f3bc12ecb23ceb76", (4326792 * 2 + 141798) * 1024),
+    "detect": ("d5870dafe3fa517a", (2237765 * 2 + 170173) * 1024),
+    "block_stats": ("4d5a55ffd1bb7642", (4349684 * 2 + 137249) * 1024),
 }
 
 
