@@ -78,25 +78,31 @@ int stats_seg_for(const sps_plan* p, int64_t nb) {
 
 int auto_stats_seg(const sps_plan* p) { return stats_seg_for(p, p->nblocks); }
 
-// Chain segments of rows whose first windows are clipped at the row start
-// (they grow from 64 samples to the full window): there the median and MAD
-// move far from block to block and the chain takes the slow queries, so the
-// row's first chain is made shorter by four window lengths in blocks (at most
-// half a segment) and the others longer (automatic segmentation only; the
-// measured optimum under drifting baselines). Fills seg (blocks of segments
-// 1, 2, ...), head (blocks of segment 0) and nseg.
-void stats_segments_clipped(const sps_plan* p, int64_t nb, int32_t& seg, int32_t& head, int32_t& nseg) {
-  seg = stats_seg_for(p, nb);
-  nseg = (int32_t)((nb + seg - 1) / seg);
+// Rows whose first windows are clipped at the row start (they grow from 64
+// samples to the full window): there the median and MAD move far from block
+// to block and the chain takes the slow queries, so the row's first chain is
+// made shorter by four window lengths in blocks (at most half a segment) and
+// the others longer (the measured optimum under drifting baselines). `nb`
+// blocks per row in `nseg` segments of `seg`; on return seg is the length of
+// segments 1, 2, ... and head that of segment 0.
+void shorten_first_segment(int64_t nb, int64_t window, int32_t nseg, int32_t& seg, int32_t& head) {
   head = seg;
-  if (p->stats_seg > 0 || nseg < 2) return;
-  const int64_t shift = std::min<int64_t>(4 * std::min<int64_t>(p->baseline_len, p->nsamp) / sps::kStride, seg / 2);
+  if (nseg < 2) return;
+  const int64_t shift = std::min<int64_t>(4 * window / sps::kStride, seg / 2);
   const int64_t seg2 = (nb + shift + nseg - 1) / nseg;
   const int64_t h = nb - (int64_t)(nseg - 1) * seg2;
   if (h >= 1 && h <= seg2) {
     seg = (int32_t)seg2;
     head = (int32_t)h;
   }
+}
+
+// Chain segments of a search's rows (automatic segmentation shortens the first).
+void stats_segments_clipped(const sps_plan* p, int64_t nb, int32_t& seg, int32_t& head, int32_t& nseg) {
+  seg = stats_seg_for(p, nb);
+  nseg = (int32_t)((nb + seg - 1) / seg);
+  head = seg;
+  if (p->stats_seg == 0) shorten_first_segment(nb, std::min<int64_t>(p->baseline_len, p->nsamp), nseg, seg, head);
 }
 
 // Positions per detection segment for rows of `npos` positions (tuning only).
@@ -986,7 +992,7 @@ namespace {
 struct BatchShape {
   int idx;
   int32_t nblocks, nw;
-  int32_t stats_seg, stats_nseg;
+  int32_t stats_seg, stats_nseg, stats_head;
   int32_t detect_seg, detect_nseg;
   int64_t ms_off, frag_off;
 };
@@ -1105,6 +1111,10 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
     seg = std::max<int64_t>(1, std::min<int64_t>(seg, s.nblocks));
     s.stats_seg = (int32_t)seg;
     s.stats_nseg = (int32_t)((s.nblocks + seg - 1) / seg);
+    s.stats_head = s.stats_seg;
+    if (b->stats_seg == 0)
+      shorten_first_segment(s.nblocks, std::min<int64_t>(it.baseline_len, it.nsamp), s.stats_nseg, s.stats_seg,
+                            s.stats_head);
     int64_t dseg = b->detect_seg > 0 ? b->detect_seg : std::max<int64_t>(total_samples / 8192, 4LL * it.max_width);
     dseg = (dseg + kDetectStep - 1) / kDetectStep * kDetectStep;
     const int64_t nmax = std::max<int64_t>(kDetectStep, (it.nsamp + kDetectStep - 1) / kDetectStep * kDetectStep);
@@ -1199,7 +1209,7 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
     a.nblocks = s.nblocks;
     a.kb_first = 0;
     a.seg_blocks = s.stats_seg;
-    a.head_blocks = s.stats_seg;
+    a.head_blocks = s.stats_head;
     a.nseg = s.stats_nseg;
     a.nchains = it.ndm * s.stats_nseg;
     a.tmin = nullptr;
