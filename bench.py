@@ -38,8 +38,8 @@ KERNEL_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md
-    "detect": ("d5870dafe3fa517a", (2237765 * 2 + 170173) * 1024),
-    "block_stats": ("4d5a55ffd1bb7642", (4349684 * 2 + 137249) * 1024),
+    "detect": ("d4c390cc81980d89", (2237764 * 2 + 170195) * 1024),
+    "block_stats": ("29c6a4c7e45bd3fa", (4349690 * 2 + 137215) * 1024),
 }
 
 
