@@ -323,6 +323,9 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain per-stage path")
+    ap.add_argument("--no-cluster", action="store_true", help="skip timing the clustering of the candidates")
+    ap.add_argument("--cluster-tol", type=int, nargs=3, default=[32, 3, 2], metavar=("TIME", "DM", "WIDTH"),
+                    help="clustering tolerances: samples, DM trials, log2 widths")
     ap.add_argument("--per-dm-rows", type=int, default=32,
                     help="rows timed for the per-DM-trial loop of the plain path (0: skip)")
     ap.add_argument("--autotune", action="store_true",
@@ -433,6 +436,27 @@ def main():
         p1.close()
         log("plain per-DM loop: %.1f ms per %d rows (from %d rows)" % (per_dm_ms, b.ndm, rows))
 
+    # candidate merging and clustering of this search's candidates (reported beside the metric)
+    cluster = None
+    if not args.no_cluster and n > 0:
+        plan.search(xd, cands, ncand, stream=stream)
+        k = sps.Clusterer(n)
+        out_c, nout = k.alloc_out(n)
+        tt, dt, wt = args.cluster_tol
+        k.run(cands, n, tt, dt, wt, out_c, nout, stream=stream)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(3):
+            k.run(cands, n, tt, dt, wt, out_c, nout, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        cms = ev0.elapsed_time(ev1) / 3
+        cluster = {"tolerances": {"samples": tt, "dm_trials": dt, "log2_width": wt}, "ms": cms, "candidates": n,
+                   "clusters": int(nout.item()), "candidates_per_s": n / (cms * 1e-3)}
+        k.close()
+        log("clustering: %.3f ms for %d candidates -> %d clusters" % (cms, n, cluster["clusters"]))
+
     samples = b.ndm * b.nsamp
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = samples * args.steps / (t1 - t0)
@@ -471,6 +495,7 @@ def main():
         "plain_per_dm_loop_ms_per_step": per_dm_ms,
         "fused_vs_per_dm_loop": (per_dm_ms / ms_per_step) if per_dm_ms else None,
         "candidates": n,
+        "cluster": cluster,
         "tuning": tuned["config"] if tuned else "library defaults",
         "cpu_baseline": cpu,
     }

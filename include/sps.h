@@ -258,6 +258,50 @@ void sps_batch_destroy(sps_batch* b);
 int sps_footprint(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baseline_len, int streaming,
                   uint64_t* bytes);
 
+/*
+ * Candidate merging and clustering (Heimdall++, Section II-B "Candidate
+ * Merging and Clustering", Section III and the last step of Algorithm 1:
+ * detections close in time, DM and filter width are grouped and each group is
+ * reported by its strongest member). The paper gives no rule or tolerances;
+ * the reading implemented is friends-of-friends: candidates a and b are
+ * linked when |sample_a - sample_b| <= time_tol, |dm_a - dm_b| <= dm_tol and
+ * |log2 width_a - log2 width_b| <= width_tol; clusters are the connected
+ * components of the links; each is reported by its member of largest S/N
+ * (equal S/N: smallest dm, then width, then sample), with the member count
+ * and the cluster's sample and DM extents.
+ *
+ * sps_cluster_create: device scratch for up to max_cands candidates per run
+ *   (about 40 bytes per candidate plus 48 MiB of time-cell tables). NULL on
+ *   error (SPS_ERR_INVALID_ARG for max_cands = 0, SPS_ERR_OOM, SPS_ERR_HIP).
+ * sps_cluster_run: clusters the n candidates at d_cands (device, caller-owned,
+ *   as written by sps_search; n <= max_cands, given by the host) on `stream`.
+ *   Writes one record per cluster to d_out (device, capacity n records; order
+ *   unspecified) and their count to *d_nout (device). Asynchronous and
+ *   stream-ordered; tolerances must be >= 0, samples within int32, dm_idx
+ *   < 2^27 and widths powers of two up to 2^31. A context serves one stream
+ *   at a time.
+ * sps_cluster_destroy: waits for the device and frees the context (NULL-safe).
+ */
+typedef struct {
+  int32_t sample;     /* best member: boxcar start */
+  uint32_t dm_idx;
+  uint32_t width;
+  float snr;
+  uint32_t members;   /* candidates in the cluster */
+  int32_t sample_lo;  /* smallest and largest sample of its members */
+  int32_t sample_hi;
+  uint32_t dm_lo;     /* smallest and largest dm_idx of its members */
+  uint32_t dm_hi;
+  uint32_t reserved;
+} sps_cluster_rec;    /* 40 bytes */
+
+typedef struct sps_clusterer sps_clusterer;
+
+sps_clusterer* sps_cluster_create(uint32_t max_cands);
+int sps_cluster_run(sps_clusterer* k, const sps_cand* d_cands, uint32_t n, int32_t time_tol, int32_t dm_tol,
+                    int32_t width_tol, hipStream_t stream, sps_cluster_rec* d_out, uint32_t* d_nout);
+void sps_cluster_destroy(sps_clusterer* k);
+
 /* Last error code of the calling thread, and a static text for a code. */
 int sps_last_error(void);
 const char* sps_error_string(int code);

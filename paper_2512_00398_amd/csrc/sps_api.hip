@@ -1291,3 +1291,82 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Candidate clustering context: one device allocation carved into the
+// scratch arrays of ClusterScratch.
+
+struct sps_clusterer {
+  uint32_t cap;
+  void* mem;
+  sps::ClusterScratch s;
+};
+
+extern "C" {
+
+sps_clusterer* sps_cluster_create(uint32_t max_cands) {
+  if (max_cands == 0) {
+    fail(SPS_ERR_INVALID_ARG);
+    return nullptr;
+  }
+  const size_t n = max_cands;
+  const size_t cells = (size_t)sps::kClusterCells + 2;
+  const size_t tiles = (size_t)sps::kClusterCells / 1024 + 1;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = (off + bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  const size_t o_order = take(4 * n), o_parent = take(4 * n), o_members = take(4 * n), o_snr = take(4 * n);
+  const size_t o_slo = take(4 * n), o_shi = take(4 * n), o_dlo = take(4 * n), o_dhi = take(4 * n);
+  const size_t o_tie = take(8 * n), o_count = take(4 * cells), o_cursor = take(4 * cells);
+  const size_t o_bsum = take(4 * tiles), o_geo = take(16);
+  sps_clusterer* k = new (std::nothrow) sps_clusterer;
+  if (!k) {
+    fail(SPS_ERR_OOM);
+    return nullptr;
+  }
+  k->cap = max_cands;
+  k->mem = nullptr;
+  if (hipMalloc(&k->mem, off) != hipSuccess) {
+    (void)hipGetLastError();
+    delete k;
+    fail(SPS_ERR_OOM);
+    return nullptr;
+  }
+  char* b = static_cast<char*>(k->mem);
+  k->s.order = reinterpret_cast<uint32_t*>(b + o_order);
+  k->s.parent = reinterpret_cast<int32_t*>(b + o_parent);
+  k->s.members = reinterpret_cast<uint32_t*>(b + o_members);
+  k->s.snrbits = reinterpret_cast<uint32_t*>(b + o_snr);
+  k->s.slo = reinterpret_cast<int32_t*>(b + o_slo);
+  k->s.shi = reinterpret_cast<int32_t*>(b + o_shi);
+  k->s.dlo = reinterpret_cast<uint32_t*>(b + o_dlo);
+  k->s.dhi = reinterpret_cast<uint32_t*>(b + o_dhi);
+  k->s.tie = reinterpret_cast<unsigned long long*>(b + o_tie);
+  k->s.count = reinterpret_cast<uint32_t*>(b + o_count);
+  k->s.cursor = reinterpret_cast<uint32_t*>(b + o_cursor);
+  k->s.bsum = reinterpret_cast<uint32_t*>(b + o_bsum);
+  k->s.geo = reinterpret_cast<int32_t*>(b + o_geo);
+  ok();
+  return k;
+}
+
+int sps_cluster_run(sps_clusterer* k, const sps_cand* d_cands, uint32_t n, int32_t time_tol, int32_t dm_tol,
+                    int32_t width_tol, hipStream_t stream, sps_cluster_rec* d_out, uint32_t* d_nout) {
+  if (!k || !d_nout || (n > 0 && (!d_cands || !d_out)) || n > k->cap || time_tol < 0 || dm_tol < 0 || width_tol < 0)
+    return fail(SPS_ERR_INVALID_ARG);
+  if (sps::launch_cluster(d_cands, n, time_tol, dm_tol, width_tol, k->s, d_out, d_nout, stream) != hipSuccess)
+    return fail(SPS_ERR_HIP);
+  return ok();
+}
+
+void sps_cluster_destroy(sps_clusterer* k) {
+  if (!k) return;
+  (void)hipDeviceSynchronize();
+  if (k->mem) (void)hipFree(k->mem);
+  delete k;
+}
+
+}  // extern "C"

@@ -146,6 +146,24 @@ struct BatchDetect {
   uint32_t* counter;
 };
 
+// Candidate clustering scratch (device arrays; n = candidates of a run).
+constexpr int kClusterCells = 1 << 22;  // time cells of the bucketing
+struct ClusterScratch {
+  uint32_t* order;    // [cap] candidate index at each bucketed position
+  int32_t* parent;    // [cap] union-find over positions (parent <= position)
+  uint32_t* members;  // [cap] per root: member count
+  uint32_t* snrbits;  //        largest S/N (float bits)
+  int32_t* slo;       //        sample extent
+  int32_t* shi;
+  uint32_t* dlo;      //        DM extent
+  uint32_t* dhi;
+  unsigned long long* tie;  // [cap] per root: smallest (dm, width, sample) key at the largest S/N
+  uint32_t* count;    // [kClusterCells + 2] cell counts, then cell starts
+  uint32_t* cursor;   // [kClusterCells + 2] scatter cursors
+  uint32_t* bsum;     // [kClusterCells / 1024 + 1] scan tile totals
+  int32_t* geo;       // [4] smallest and largest sample, cell width, cells
+};
+
 // Host-side launchers (defined in the .hip files).
 hipError_t launch_block_stats(const StatsArgs& a, int hist_bins, hipStream_t s);
 hipError_t launch_detect(const DetectArgs& a, hipStream_t s);
@@ -163,5 +181,7 @@ hipError_t launch_fixup_batch(const BatchDetect& b, const int32_t* d_offs, int t
 hipError_t launch_batch_zero(uint32_t* const* d_ncand, int n, uint32_t* counters, hipStream_t s);
 hipError_t launch_plain_prepare(const PlainArgs& a, hipStream_t s);
 hipError_t launch_plain_width(const PlainArgs& a, hipStream_t s);
+hipError_t launch_cluster(const sps_cand* c, uint32_t n, int time_tol, int dm_tol, int width_tol,
+                          const ClusterScratch& s, sps_cluster_rec* out, uint32_t* nout, hipStream_t st);
 
 }  // namespace sps

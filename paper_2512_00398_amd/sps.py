@@ -36,6 +36,10 @@ ATTR_BLOCK_STRIDE = 18
 
 BLOCK_STRIDE = 64
 CAND_DTYPE = np.dtype([("sample", "<i4"), ("dm_idx", "<u4"), ("width", "<u4"), ("snr", "<f4")])
+# sps_cluster_rec (40 bytes)
+CLUSTER_DTYPE = np.dtype([("sample", "<i4"), ("dm_idx", "<u4"), ("width", "<u4"), ("snr", "<f4"),
+                          ("members", "<u4"), ("sample_lo", "<i4"), ("sample_hi", "<i4"), ("dm_lo", "<u4"),
+                          ("dm_hi", "<u4"), ("reserved", "<u4")])
 
 # (name, restype, argtypes) of every exported entry point declared in include/sps.h
 _P = ctypes.c_void_p
@@ -63,6 +67,10 @@ EXPORTS = [
     ("sps_batch_set", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64]),
     ("sps_batch_search", ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
     ("sps_batch_destroy", None, [_P]),
+    ("sps_cluster_create", _P, [ctypes.c_uint32]),
+    ("sps_cluster_run", ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
+                                       _P]),
+    ("sps_cluster_destroy", None, [_P]),
     ("sps_last_error", ctypes.c_int, []),
     ("sps_error_string", ctypes.c_char_p, [ctypes.c_int]),
 ]
@@ -378,3 +386,56 @@ def search(series, max_width: int, baseline_len: int, snr_thresh: float, capacit
         p.search(series, cands, ncand, plain=plain)
         torch.cuda.synchronize()
         return cands_to_numpy(cands, ncand, p.max_cands)
+
+
+class Clusterer:
+    """Candidate merging and clustering on the GPU (see include/sps.h)."""
+
+    def __init__(self, max_cands: int):
+        lib = load()
+        self.max_cands = int(max_cands)
+        self._h = lib.sps_cluster_create(self.max_cands)
+        if not self._h:
+            raise SpsError(lib.sps_last_error(), "sps_cluster_create")
+
+    def alloc_out(self, n: Optional[int] = None):
+        """Output records (int32 [n][10] GPU tensor) and their count (int32 [1])."""
+        import torch
+        n = self.max_cands if n is None else int(n)
+        return (torch.empty((max(1, n), 10), dtype=torch.int32, device="cuda"),
+                torch.zeros((1,), dtype=torch.int32, device="cuda"))
+
+    def run(self, cands, n: int, time_tol: int, dm_tol: int, width_tol: int, out, nout, stream=None) -> None:
+        """Cluster the first n records of cands (int32 [capacity][4] GPU tensor) into out / nout."""
+        if int(n) > cands.shape[0] or int(n) > out.shape[0]:
+            raise ValueError("n exceeds the candidate or output capacity")
+        rc = load().sps_cluster_run(self._h, cands.data_ptr(), int(n), int(time_tol), int(dm_tol), int(width_tol),
+                                    _stream_handle(stream), out.data_ptr(), nout.data_ptr())
+        if rc:
+            raise SpsError(rc, "sps_cluster_run")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().sps_cluster_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def clusters_to_numpy(out, nout) -> np.ndarray:
+    """Copy the cluster records to a structured array sorted (dm, width, sample) of their best member."""
+    n = int(nout.item()) & 0xFFFFFFFF
+    a = out[:n].cpu().numpy().view(CLUSTER_DTYPE).reshape(-1)
+    if a.size:
+        a = a[np.lexsort((a["sample"], a["width"], a["dm_idx"]))]
+    return a

@@ -98,6 +98,10 @@ int main(void) {
   if (sps_footprint(64, 16384, 64, 4096, 0, &bytes) != SPS_OK || bytes == 0) return 4;
   sps_plan_destroy(NULL);
   sps_batch_destroy(NULL);
+  if (sps_cluster_create(0) != NULL || sps_last_error() != SPS_ERR_INVALID_ARG) return 5;
+  if (sps_cluster_run(NULL, NULL, 0, 1, 1, 1, NULL, NULL, NULL) != SPS_ERR_INVALID_ARG) return 6;
+  sps_cluster_destroy(NULL);
+  if (sizeof(sps_cluster_rec) != 40) return 7;
   printf("%s\n", sps_error_string(SPS_ERR_DOMAIN));
   return 0;
 }
