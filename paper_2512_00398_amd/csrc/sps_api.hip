@@ -1318,10 +1318,10 @@ sps_clusterer* sps_cluster_create(uint32_t max_cands) {
     off = (off + bytes + 255) & ~(size_t)255;
     return at;
   };
-  const size_t o_order = take(4 * n), o_parent = take(4 * n), o_members = take(4 * n), o_snr = take(4 * n);
+  const size_t o_sorted = take(16 * n), o_parent = take(4 * n), o_members = take(4 * n), o_snr = take(4 * n);
   const size_t o_slo = take(4 * n), o_shi = take(4 * n), o_dlo = take(4 * n), o_dhi = take(4 * n);
   const size_t o_tie = take(8 * n), o_count = take(4 * cells), o_cursor = take(4 * cells);
-  const size_t o_bsum = take(4 * tiles), o_geo = take(16);
+  const size_t o_bsum = take(4 * tiles), o_geo = take(32);
   sps_clusterer* k = new (std::nothrow) sps_clusterer;
   if (!k) {
     fail(SPS_ERR_OOM);
@@ -1336,7 +1336,7 @@ sps_clusterer* sps_cluster_create(uint32_t max_cands) {
     return nullptr;
   }
   char* b = static_cast<char*>(k->mem);
-  k->s.order = reinterpret_cast<uint32_t*>(b + o_order);
+  k->s.sorted = reinterpret_cast<sps_cand*>(b + o_sorted);
   k->s.parent = reinterpret_cast<int32_t*>(b + o_parent);
   k->s.members = reinterpret_cast<uint32_t*>(b + o_members);
   k->s.snrbits = reinterpret_cast<uint32_t*>(b + o_snr);

@@ -149,7 +149,7 @@ struct BatchDetect {
 // Candidate clustering scratch (device arrays; n = candidates of a run).
 constexpr int kClusterCells = 1 << 22;  // time cells of the bucketing
 struct ClusterScratch {
-  uint32_t* order;    // [cap] candidate index at each bucketed position
+  sps_cand* sorted;   // [cap] candidates in bucket order
   int32_t* parent;    // [cap] union-find over positions (parent <= position)
   uint32_t* members;  // [cap] per root: member count
   uint32_t* snrbits;  //        largest S/N (float bits)
@@ -161,7 +161,7 @@ struct ClusterScratch {
   uint32_t* count;    // [kClusterCells + 2] cell counts, then cell starts
   uint32_t* cursor;   // [kClusterCells + 2] scatter cursors
   uint32_t* bsum;     // [kClusterCells / 1024 + 1] scan tile totals
-  int32_t* geo;       // [4] smallest and largest sample, cell width, cells
+  int32_t* geo;       // [8] cell geometry (sample and DM ranges, cell sizes)
 };
 
 // Host-side launchers (defined in the .hip files).

@@ -83,6 +83,17 @@ __device__ __forceinline__ int wave_max_u(int v) {
   return readlane(v, 63);
 }
 
+// Minimum over the 64 lanes, returned wave-uniform.
+__device__ __forceinline__ int wave_min_u(int v) {
+  v = min_step<0xb1>(v);
+  v = min_step<0x4e>(v);
+  v = min_step<0x141>(v);
+  v = min_step<0x140>(v);
+  v = min_step<0x142, 0xa>(v);
+  v = min_step<0x143, 0xc>(v);
+  return readlane(v, 63);
+}
+
 template <int CTRL, int RM>
 __device__ __forceinline__ void max_step4(int& a, int& b, int& c, int& d) {
   a = max_step<CTRL, RM>(a);

@@ -76,6 +76,10 @@ def test_edge_cases():
     check(c, 5, 3, 1, "int32-range")
     c = _random_cands(rng, 4000, 0, 100000, 100, 13, ties=True)
     check(c, 1 << 30, 1 << 20, 31, "unbounded")
+    c = _random_cands(rng, 6000, -7, 3000, (1 << 27) - 1, 13)  # DM range beyond the cell table: wide DM cells
+    c["dm_idx"][::7] = c["dm_idx"][::7] % 64  # and a dense corner that links
+    c = c[np.unique(np.stack([c["sample"], c["dm_idx"], c["width"]], 1), axis=0, return_index=True)[1]]
+    check(c, 9, 5, 1, "dm-range")
 
 
 def test_search_output_small_config():
