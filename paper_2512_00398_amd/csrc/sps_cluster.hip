@@ -253,7 +253,10 @@ __global__ void k_cluster_link(uint32_t n, int tt, int dt, int wt, ClusterScratc
   const uint32_t cell = cell_of(s, a.sample, a.dm_idx, ct, cd);
   const int nd = s.geo[3], nt = s.geo[7];
   const int la = log2w(a.width);
-  auto join = [&](uint32_t q) { unite(s.parent, (int)p, (int)q); };
+  auto join = [&](uint32_t q) {
+    if (ld_relaxed(&s.parent[p]) == ld_relaxed(&s.parent[q])) return;  // same tree, nothing to look up
+    unite(s.parent, (int)p, (int)q);
+  };
   // cells are numbered row by row (time), DM cells within a row: a run of
   // neighbouring DM cells is one contiguous range of positions
   for (uint32_t q = p + 1, e = s.count[cell + 1]; q < e; ++q)
