@@ -35,6 +35,11 @@ design notes):
    ``(dm_idx, sample=i*, width=w, snr=(float32) snr(i*))``.
 8. Streaming is item 1-7 applied to the concatenation of the gulps; a batch is
    item 1-7 applied to every item on its own.
+9. Centred-window variant (a plan option; the paper's "moving average" does
+   not say where the window sits): the window of block k reaches ``lead =
+   max(0, floor((L - S) / 2))`` samples past the block's end,
+   ``W_k = x[max(0, e_k + lead - L) : min(N, e_k + lead)]``, so it is centred
+   on the block (exactly when L - S is even); everything else is unchanged.
 """
 from __future__ import annotations
 
@@ -71,8 +76,14 @@ def lower_median(values: np.ndarray) -> int:
     return int(np.partition(values, r)[r])
 
 
-def block_median_mad(x_row: np.ndarray, baseline_len: int, stride: int = BLOCK_STRIDE) -> Tuple[np.ndarray, np.ndarray]:
-    """Readings 2-4: per-block lower median and MAD of the trailing window.
+def window_lead(baseline_len: int, stride: int = BLOCK_STRIDE, centered: bool = False) -> int:
+    """Reading 9: samples the baseline window reaches past its block (0: trailing)."""
+    return max(0, (baseline_len - stride) // 2) if centered else 0
+
+
+def block_median_mad(x_row: np.ndarray, baseline_len: int, stride: int = BLOCK_STRIDE,
+                     lead: int = 0) -> Tuple[np.ndarray, np.ndarray]:
+    """Readings 2-4 (and 9 with lead > 0): per-block lower median and MAD of the window.
 
     Baseline removal and normalisation stages (Section II-B; Algorithm 1's
     per-trial kernels). Returns int64 arrays ``m`` and ``mad`` of length
@@ -84,8 +95,9 @@ def block_median_mad(x_row: np.ndarray, baseline_len: int, stride: int = BLOCK_S
     m = np.empty(nb, dtype=np.int64)
     mad = np.empty(nb, dtype=np.int64)
     for k in range(nb):
-        e = min(k * stride + stride, n)
-        lo = max(0, e - baseline_len)
+        end = min(k * stride + stride, n) + lead
+        lo = max(0, end - baseline_len)
+        e = min(n, end)
         window = x_row[lo:e]
         m[k] = lower_median(window)
         mad[k] = lower_median(np.abs(window - m[k]))
@@ -145,9 +157,9 @@ def peaks(above: np.ndarray, snr: np.ndarray) -> List[Tuple[int, float]]:
 
 
 def search_row(x_row: np.ndarray, dm_idx: int, max_width: int, baseline_len: int, theta: float,
-               stride: int = BLOCK_STRIDE, with_stats: bool = False):
+               stride: int = BLOCK_STRIDE, with_stats: bool = False, lead: int = 0):
     """Stages of one DM trial in the paper's order: baseline, normalise, filter, detect."""
-    m, mad = block_median_mad(x_row, baseline_len, stride)
+    m, mad = block_median_mad(x_row, baseline_len, stride, lead)
     r = residual(x_row, m, stride)
     cands = []
     for w in widths(max_width):
@@ -176,7 +188,7 @@ def sort_cands(c: np.ndarray) -> np.ndarray:
 
 def search(block: np.ndarray, max_width: int, baseline_len: int, theta: float,
            rows: Optional[Iterable[int]] = None, stride: int = BLOCK_STRIDE,
-           row_ids: Optional[Sequence[int]] = None, with_stats: bool = False):
+           row_ids: Optional[Sequence[int]] = None, with_stats: bool = False, centered: bool = False):
     """Search every row of ``block`` ([ndm][N]); candidates sorted (dm, width, sample).
 
     ``rows`` restricts the search to those rows of ``block``; ``row_ids``
@@ -191,7 +203,8 @@ def search(block: np.ndarray, max_width: int, baseline_len: int, theta: float,
     parts, ms, mads = [], [], []
     for r in rr:
         d = r if row_ids is None else int(row_ids[r])
-        c, m, mad = search_row(block[r], d, max_width, baseline_len, theta, stride, with_stats=True)
+        c, m, mad = search_row(block[r], d, max_width, baseline_len, theta, stride, with_stats=True,
+                               lead=window_lead(baseline_len, stride, centered))
         parts.append(c)
         ms.append(m)
         mads.append(mad)

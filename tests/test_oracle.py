@@ -227,3 +227,88 @@ def test_widths_and_edges():
     assert (c["width"] <= 10).all()
     # a single-sample row: MAD = 0, nothing
     assert oracle.search(np.ones((1, 1), np.float32), 4, 4, 0.1).size == 0
+
+
+def brute_centred_stats(x, L, S):
+    """Lower median and MAD of windows centred on each block's middle sample
+    (c - L/2 .. c + L/2, clipped to the row), for rows of whole blocks."""
+    n = len(x)
+    ms, mads = [], []
+    for k in range(n // S):
+        c = k * S + S // 2
+        w = sorted(x[max(0, c - L // 2):min(n, c + L // 2)])
+        r = (len(w) - 1) // 2
+        ms.append(w[r])
+        mads.append(sorted(abs(v - w[r]) for v in w)[r])
+    return ms, mads
+
+
+@pytest.mark.parametrize("n,L,S,seed", [(64, 16, 8, 0), (96, 40, 8, 1), (256, 64, 64, 2), (512, 192, 64, 3),
+                                        (640, 4096, 64, 4), (48, 20, 4, 5)])
+def test_centred_window_brute_force(n, L, S, seed):
+    # rows of whole blocks and L - S even: the window reaches (L - S) / 2 past
+    # its block, i.e. it is centred on the block's middle
+    rng = np.random.default_rng(seed)
+    x = rng.integers(-50, 50, size=n)
+    x[: n // 3] = rng.integers(0, 3, size=n // 3)
+    lead = oracle.window_lead(L, S, centered=True)
+    assert lead == (L - S) // 2
+    m, mad = oracle.block_median_mad(x, L, S, lead)
+    bm, bmad = brute_centred_stats(x.tolist(), L, S)
+    assert m.tolist() == bm and mad.tolist() == bmad
+
+
+def test_centred_window_time_reversal():
+    # A centred window maps to a centred window under time reversal: block k
+    # of the reversed row has the statistics of block nb-1-k of the row.
+    rng = np.random.default_rng(21)
+    for n, L in ((1024, 320), (2048, 1000), (640, 64)):
+        x = rng.integers(-300, 300, size=n)
+        lead = oracle.window_lead(L, 64, centered=True)
+        m, mad = oracle.block_median_mad(x, L, 64, lead)
+        mr, madr = oracle.block_median_mad(x[::-1].copy(), L, 64, lead)
+        assert np.array_equal(mr, m[::-1]) and np.array_equal(madr, mad[::-1])
+
+
+def test_centred_window_short_is_trailing():
+    # L <= S: nothing to centre, the window is the trailing one
+    assert oracle.window_lead(64, 64, centered=True) == 0 and oracle.window_lead(10, 64, centered=True) == 0
+    x = np.random.default_rng(3).integers(-9, 9, size=500)
+    a = oracle.search(x[None, :].astype(np.float32), 8, 40, 2.0, centered=True)
+    b = oracle.search(x[None, :].astype(np.float32), 8, 40, 2.0)
+    assert np.array_equal(a, b)
+
+
+def test_centred_search_matches_explicit_loops():
+    rng = np.random.default_rng(8)
+    S, L = 64, 320
+    x = rng.integers(-20, 20, size=640)
+    x[300:306] += 60
+    ms, mads = brute_centred_stats(x.tolist(), L, S)
+    # the explicit search with these statistics (whole blocks, so every block is centred)
+    th = 3.0
+    got = oracle.search(x[None, :].astype(np.float32), 16, L, th, centered=True)
+    r = [int(x[t]) - ms[t // S] for t in range(len(x))]
+    out, w = [], 1
+    while w <= 16:
+        vals = []
+        for i in range(len(x) - w + 1):
+            mad = mads[(i + w // 2) // S]
+            s = sum(r[i:i + w])
+            v = s / ((K * mad) * math.sqrt(w)) if mad else None
+            vals.append(v if v is not None and v > th else None)
+        i = 0
+        while i < len(vals):
+            if vals[i] is None:
+                i += 1
+                continue
+            j, bi = i, i
+            while j < len(vals) and vals[j] is not None:
+                if vals[j] > vals[bi]:
+                    bi = j
+                j += 1
+            out.append((bi, 0, w, float(np.float32(vals[bi]))))
+            i = j
+        w *= 2
+    assert as_tuples(got) == sorted(out, key=lambda c: (c[1], c[2], c[0]))
+    assert len(out) > 0
