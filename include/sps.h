@@ -142,6 +142,13 @@ int sps_search_plain(sps_plan* plan, const float* d_series, hipStream_t stream, 
 #define SPS_ATTR_HIST_BINS 4      /* fine histogram span in values: 4096 or 16384 (tuning) */
 #define SPS_ATTR_TIMING 5         /* 1: record HIP events around every kernel of a search */
 #define SPS_ATTR_VALIDATE 6       /* 1: check the input domain before each search (host-synchronous) */
+#define SPS_ATTR_WINDOW 7         /* baseline window placement, part of the arithmetic: 0 (default) trailing,
+                                     W_k = x[max(0, e_k - L) : e_k]; 1 centred on its block, the window
+                                     reaching lead = max(0, (L - 64) / 2) samples past the block's end,
+                                     W_k = x[max(0, e_k + lead - L) : min(N, e_k + lead)]
+                                     (Section II-B's moving baseline; the paper does not place the window).
+                                     Plans and batches; a stream refuses a plan with 1 (its blocks would
+                                     wait for lead samples of the next gulp). */
 #define SPS_ATTR_NBLOCKS 16       /* read-only: ceil(nsamp / 64) */
 #define SPS_ATTR_NWIDTHS 17       /* read-only: number of boxcar widths */
 #define SPS_ATTR_BLOCK_STRIDE 18  /* read-only: S = SPS_BLOCK_STRIDE, part of the arithmetic (never tuned) */
@@ -174,7 +181,8 @@ int sps_timing_read(sps_plan* plan, double* ms_out, int64_t* nsearch);
  *
  * sps_stream_create: `plan` gives the gulp shape (ndm x nsamp, nsamp a
  *   multiple of 64) and parameters; it must outlive the stream, and the
- *   stream must not run concurrently with another use of the plan.
+ *   stream must not run concurrently with another use of the plan. A plan
+ *   with SPS_ATTR_WINDOW = 1 is refused (SPS_ERR_INVALID_ARG).
  * sps_stream_push: search one gulp (device FP32 [ndm][nsamp]); candidates are
  *   those whose runs ended during this gulp, with `sample` relative to the
  *   gulp's first sample (negative: the boxcar started in an earlier gulp).
@@ -226,7 +234,8 @@ void sps_stream_destroy(sps_stream* s);
  *   SPS_ERR_INVALID_ARG (any item invalid: nothing enqueued), SPS_ERR_OOM,
  *   SPS_ERR_HIP.
  * sps_batch_set: tuning attributes SPS_ATTR_STATS_SEG, SPS_ATTR_DETECT_SEG,
- *   SPS_ATTR_HIST_BINS (same meaning as for plans; apply to every item).
+ *   SPS_ATTR_HIST_BINS, and SPS_ATTR_WINDOW (same meaning as for plans; apply
+ *   to every item).
  * sps_batch_destroy: waits for the context's work and frees it (NULL-safe).
  */
 typedef struct {

@@ -22,6 +22,7 @@ struct sps_plan {
   int32_t stats_seg;   // blocks per baseline chain, 0 = auto
   int32_t detect_seg;  // samples per detection segment, 0 = auto
   int32_t hist_bins;   // 4096 or 16384
+  int32_t window;      // SPS_ATTR_WINDOW: 0 trailing, 1 centred (changes results)
   int device;
   // scratch owned by the plan
   int32_t* d_med;
@@ -85,6 +86,16 @@ int auto_stats_seg(const sps_plan* p) { return stats_seg_for(p, p->nblocks); }
 // the others longer (the measured optimum under drifting baselines). `nb`
 // blocks per row in `nseg` segments of `seg`; on return seg is the length of
 // segments 1, 2, ... and head that of segment 0.
+// Samples a block's baseline window reaches past the block's end.
+int32_t window_lead(int32_t baseline_len, int window) {
+  return window == 1 ? std::max<int32_t>(0, (baseline_len - sps::kStride) / 2) : 0;
+}
+
+// Positions up to N + lead + 64 stay inside int32 arithmetic.
+bool window_fits(int64_t nsamp, int32_t baseline_len, int window) {
+  return nsamp + window_lead(baseline_len, window) + sps::kStride <= (int64_t)INT32_MAX - 8192;
+}
+
 void shorten_first_segment(int64_t nb, int64_t window, int32_t nseg, int32_t& seg, int32_t& head) {
   head = seg;
   if (nseg < 2) return;
@@ -354,6 +365,10 @@ int sps_plan_set(sps_plan* p, int attr, int64_t v) {
       if (v != 0 && v != 1) return fail(SPS_ERR_INVALID_ARG);
       p->validate = (int)v;
       return ok();
+    case SPS_ATTR_WINDOW:
+      if ((v != 0 && v != 1) || !window_fits(p->nsamp, p->baseline_len, (int)v)) return fail(SPS_ERR_INVALID_ARG);
+      p->window = (int32_t)v;
+      return ok();
     default:
       return fail(SPS_ERR_INVALID_ARG);
   }
@@ -368,6 +383,7 @@ int sps_plan_get(const sps_plan* p, int attr, int64_t* v) {
     case SPS_ATTR_HIST_BINS: *v = p->hist_bins; break;
     case SPS_ATTR_TIMING: *v = p->timing; break;
     case SPS_ATTR_VALIDATE: *v = p->validate; break;
+    case SPS_ATTR_WINDOW: *v = p->window; break;
     case SPS_ATTR_NBLOCKS: *v = p->nblocks; break;
     case SPS_ATTR_BLOCK_STRIDE: *v = sps::kStride; break;
     case SPS_ATTR_NWIDTHS: *v = p->nw; break;
@@ -395,6 +411,7 @@ static int launch_stats(sps_plan* p, const float* d_series, hipStream_t stream, 
   a.Hx = 0;
   a.N = p->nsamp;
   a.L = p->baseline_len;
+  a.lead = window_lead(p->baseline_len, p->window);
   a.nblocks = p->nblocks;
   a.kb_first = 0;
   stats_segments_clipped(p, p->nblocks, a.seg_blocks, a.head_blocks, a.nseg);
@@ -661,6 +678,7 @@ int sps_stream_create(sps_plan* p, sps_stream** out) {
   if (!p || !out) return fail(SPS_ERR_INVALID_ARG);
   *out = nullptr;
   if (p->nsamp % sps::kStride != 0) return fail(SPS_ERR_INVALID_ARG);  // gulps must hold whole blocks
+  if (p->window != 0) return fail(SPS_ERR_INVALID_ARG);  // a centred window would wait for the next gulp
   sps_stream* s = new (std::nothrow) sps_stream;
   if (!s) return fail(SPS_ERR_OOM);
   std::memset(s, 0, sizeof(*s));
@@ -723,6 +741,7 @@ int stream_enqueue(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_c
   a.Hx = s->Hx;
   a.N = s->Nv;
   a.L = p->baseline_len;
+  a.lead = 0;  // streams use the trailing window only
   a.nblocks = s->nbv;
   a.kb_first = s->Hb;
   a.seg_blocks = stats_seg_for(p, s->nbv - s->Hb);
@@ -973,6 +992,7 @@ int sps_footprint(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baselin
 struct sps_batch {
   int device;
   int32_t stats_seg, detect_seg, hist_bins;
+  int32_t window;      // SPS_ATTR_WINDOW for every item
   int32_t* d_ms;       // medians then MADs of every item
   int64_t ms_cap;      // int32 records
   sps::RunSum* d_frag;
@@ -1059,6 +1079,10 @@ int sps_batch_set(sps_batch* b, int attr, int64_t v) {
       if (v != 4096 && v != 16384) return fail(SPS_ERR_INVALID_ARG);
       b->hist_bins = (int32_t)v;
       return ok();
+    case SPS_ATTR_WINDOW:
+      if (v != 0 && v != 1) return fail(SPS_ERR_INVALID_ARG);
+      b->window = (int32_t)v;
+      return ok();
     default:
       return fail(SPS_ERR_INVALID_ARG);
   }
@@ -1080,7 +1104,8 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
   if (!b || n < 0 || (n > 0 && !items)) return fail(SPS_ERR_INVALID_ARG);
   if (n == 0) return ok();
   for (int32_t i = 0; i < n; ++i)
-    if (!item_valid(items[i])) return fail(SPS_ERR_INVALID_ARG);
+    if (!item_valid(items[i]) || !window_fits(items[i].nsamp, items[i].baseline_len, b->window))
+      return fail(SPS_ERR_INVALID_ARG);
 
   // Shapes. Chain and segment lengths follow the single-block rules, sized
   // for the whole batch so that the queue holds many more tasks than there
@@ -1206,6 +1231,7 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
     a.ld = it.nsamp;
     a.N = (int32_t)it.nsamp;
     a.L = it.baseline_len;
+    a.lead = window_lead(it.baseline_len, b->window);
     a.nblocks = s.nblocks;
     a.kb_first = 0;
     a.seg_blocks = s.stats_seg;

@@ -46,6 +46,7 @@ struct StatsArgs {
   int64_t ldh;
   int32_t Hx;
   int32_t N, L;        // virtual row length, baseline window
+  int32_t lead;        // samples the window reaches past its block's end (0: trailing)
   int32_t nblocks;     // ceil(N / 64): row stride of med / mad
   int32_t kb_first;    // first block computed (blocks below it are carried in)
   int32_t seg_blocks;  // blocks per chain segment (segments 1, 2, ...)

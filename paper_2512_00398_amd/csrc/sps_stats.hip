@@ -1,7 +1,9 @@
 // sps_stats.hip - baseline removal and normalisation stages (Heimdall++,
 // Section II-B): per 64-sample block k of every row, the lower median m_k and
 // the lower median absolute deviation MAD_k of the trailing window
-// W_k = x[max(0, e_k - L) : e_k], e_k = min(64k + 64, N). Results are exact.
+// W_k = x[max(0, e_k - L) : e_k], e_k = min(64k + 64, N), or of the window
+// centred on the block, which reaches `lead` = (L - 64) / 2 samples further:
+// W_k = x[max(0, e_k + lead - L) : min(N, e_k + lead)]. Results are exact.
 //
 // Design (gfx950, wave64). One wave owns one "chain": a contiguous run of
 // blocks of one row, walked in order. The wave keeps a counting histogram of
@@ -380,7 +382,7 @@ __device__ __forceinline__ void stats_chain(const StatsArgs& a, const int chain,
   // segment 0 has head_blocks blocks, the others seg_blocks each
   const int kb0 = a.kb_first + (seg == 0 ? 0 : a.head_blocks + (seg - 1) * a.seg_blocks);
   const int kb1 = min(a.nblocks, seg == 0 ? a.kb_first + a.head_blocks : kb0 + a.seg_blocks);
-  const int N = a.N, L = a.L;
+  const int N = a.N, L = a.L, lead = a.lead;
   const int t0 = a.tmin ? *a.tmin : 0;
   Chain<NB, VIRT> c;
   c.H = H;
@@ -392,8 +394,12 @@ __device__ __forceinline__ void stats_chain(const StatsArgs& a, const int chain,
   int32_t* med = a.med + (int64_t)row * a.nblocks;
   int32_t* mad = a.mad + (int64_t)row * a.nblocks;
 
+  // Block k's window is [max(t0, E_k - L), min(N, E_k)) with E_k = min(64k + 64, N) + lead:
+  // from block k-1 to k the samples [min(N, E_{k-1}), min(N, E_k)) enter it and
+  // [max(t0, E_{k-1} - L), max(t0, E_k - L)) leave it, at most 64 each.
   {
-    const int e = min(kb0 * kStride + kStride, N), lo = max(t0, e - L);
+    const int E = min(kb0 * kStride + kStride, N) + lead;
+    const int e = min(N, E), lo = max(t0, E - L);
     c.n = e - lo;
     chain_init(c, lo, e, min(N, max(e, lo + L)));
     if (lane == 0) { med[kb0] = c.m; mad[kb0] = c.d; }
@@ -405,8 +411,8 @@ __device__ __forceinline__ void stats_chain(const StatsArgs& a, const int chain,
   // compiler unsure how many are in flight, and it would then wait for all of
   // them, the prefetch included, before each block.
   auto fetch = [&](int kk, float& va, float& vb) {
-    const int ep = min(kk * kStride, N), e = min(kk * kStride + kStride, N);
-    const int lp = max(t0, ep - L), l2 = max(t0, e - L);
+    const int Ep = min(kk * kStride, N) + lead, E = min(kk * kStride + kStride, N) + lead;
+    const int ep = min(N, Ep), e = min(N, E), lp = max(t0, Ep - L), l2 = max(t0, E - L);
     const float ra = c.row.at(min(ep + lane, N - 1)), rb = c.row.at(min(lp + lane, N - 1));
     va = (lane < e - ep) ? ra : 0.f;
     vb = (lane < l2 - lp) ? rb : 0.f;
@@ -422,8 +428,8 @@ __device__ __forceinline__ void stats_chain(const StatsArgs& a, const int chain,
       const float va = pa[j], vb = pb[j];
       fetch(kk + 4, pa[j], pb[j]);
       if (kk < kb1) {
-        const int ep = min(kk * kStride, N), e = min(kk * kStride + kStride, N);
-        const int lp = max(t0, ep - L), l2 = max(t0, e - L);
+        const int Ep = min(kk * kStride, N) + lead, E = min(kk * kStride + kStride, N) + lead;
+        const int ep = min(N, Ep), e = min(N, E), lp = max(t0, Ep - L), l2 = max(t0, E - L);
         chain_step(c, l2, e, lane < e - ep, (int)va, lane < l2 - lp, (int)vb);
         // every lane stores the same (wave-uniform) values: no branch around the stores
         med[kk] = c.m;

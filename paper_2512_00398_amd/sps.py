@@ -28,6 +28,7 @@ ATTR_DETECT_SEG = 3
 ATTR_HIST_BINS = 4
 ATTR_TIMING = 5
 ATTR_VALIDATE = 6
+ATTR_WINDOW = 7  # 0 trailing baseline window (default), 1 centred on its block
 NSTAGES = 4
 STAGES = ("block_stats", "detect", "fixup", "plain")
 ATTR_NBLOCKS = 16
