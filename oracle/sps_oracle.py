@@ -40,6 +40,12 @@ design notes):
    max(0, floor((L - S) / 2))`` samples past the block's end,
    ``W_k = x[max(0, e_k + lead - L) : min(N, e_k + lead)]``, so it is centred
    on the block (exactly when L - S is even); everything else is unchanged.
+10. Row-normalisation variant (a plan option; Section II-B's "RMS scaling"
+    read as one noise scale per DM trial and chunk): the residual of item 5
+    is computed as before, and every block of the row takes the one value
+    ``MAD_row`` = lower median of ``|r_t - c|`` over the whole row, where
+    ``c`` is the lower median of ``r_t``; items 6-7 then use it in place of
+    ``MAD_{k*}``. The medians ``m_k`` are unchanged.
 """
 from __future__ import annotations
 
@@ -111,6 +117,12 @@ def residual(x_row: np.ndarray, m: np.ndarray, stride: int = BLOCK_STRIDE) -> np
     return x_row - m[t // stride]
 
 
+def row_mad(r: np.ndarray) -> int:
+    """Reading 10: lower median absolute deviation of the whole row's residual about its lower median."""
+    c = lower_median(r)
+    return lower_median(np.abs(r - c))
+
+
 def boxcar(r: np.ndarray, w: int) -> np.ndarray:
     """Reading 5, second half: S_w(i) = sum of r over [i, i+w), i = 0 .. N-w (matched filter)."""
     n = r.size
@@ -157,10 +169,12 @@ def peaks(above: np.ndarray, snr: np.ndarray) -> List[Tuple[int, float]]:
 
 
 def search_row(x_row: np.ndarray, dm_idx: int, max_width: int, baseline_len: int, theta: float,
-               stride: int = BLOCK_STRIDE, with_stats: bool = False, lead: int = 0):
+               stride: int = BLOCK_STRIDE, with_stats: bool = False, lead: int = 0, row_norm: bool = False):
     """Stages of one DM trial in the paper's order: baseline, normalise, filter, detect."""
     m, mad = block_median_mad(x_row, baseline_len, stride, lead)
     r = residual(x_row, m, stride)
+    if row_norm:
+        mad = np.full(mad.size, row_mad(r), dtype=np.int64)
     cands = []
     for w in widths(max_width):
         sw = boxcar(r, w)
@@ -188,13 +202,15 @@ def sort_cands(c: np.ndarray) -> np.ndarray:
 
 def search(block: np.ndarray, max_width: int, baseline_len: int, theta: float,
            rows: Optional[Iterable[int]] = None, stride: int = BLOCK_STRIDE,
-           row_ids: Optional[Sequence[int]] = None, with_stats: bool = False, centered: bool = False):
+           row_ids: Optional[Sequence[int]] = None, with_stats: bool = False, centered: bool = False,
+           row_norm: bool = False):
     """Search every row of ``block`` ([ndm][N]); candidates sorted (dm, width, sample).
 
     ``rows`` restricts the search to those rows of ``block``; ``row_ids``
     gives the DM index reported for each row of ``block`` (default: the row's
     position). With ``with_stats`` also returns int64 ``m`` and ``mad`` of
-    shape ``[len(rows)][ceil(N/S)]``.
+    shape ``[len(rows)][ceil(N/S)]``. ``centered`` and ``row_norm`` select
+    readings 9 and 10.
     """
     block = np.asarray(block)
     if block.ndim != 2:
@@ -204,7 +220,7 @@ def search(block: np.ndarray, max_width: int, baseline_len: int, theta: float,
     for r in rr:
         d = r if row_ids is None else int(row_ids[r])
         c, m, mad = search_row(block[r], d, max_width, baseline_len, theta, stride, with_stats=True,
-                               lead=window_lead(baseline_len, stride, centered))
+                               lead=window_lead(baseline_len, stride, centered), row_norm=row_norm)
         parts.append(c)
         ms.append(m)
         mads.append(mad)

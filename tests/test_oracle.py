@@ -33,11 +33,16 @@ def brute_stats(x, L, S):
     return ms, mads
 
 
-def brute_search_row(x, dm, max_width, L, theta, S):
-    """Whole search for one row with explicit loops only."""
+def brute_search_row(x, dm, max_width, L, theta, S, row_norm=False):
+    """Whole search for one row with explicit loops only (row_norm: one MAD
+    for the row, of the residual about its lower median)."""
     ms, mads = brute_stats(x, L, S)
     n = len(x)
     r = [x[t] - ms[t // S] for t in range(n)]
+    if row_norm:
+        sr = sorted(r)
+        c = sr[(n - 1) // 2]
+        mads = [sorted(abs(v - c) for v in r)[(n - 1) // 2]] * len(mads)
     th = float(np.float32(theta))
     out = []
     w = 1
@@ -312,3 +317,53 @@ def test_centred_search_matches_explicit_loops():
         w *= 2
     assert as_tuples(got) == sorted(out, key=lambda c: (c[1], c[2], c[0]))
     assert len(out) > 0
+
+
+@pytest.mark.parametrize("n,L,S,maxw,theta,seed", [(200, 50, 8, 16, 3.0, 0), (333, 90, 16, 32, 2.5, 1),
+                                                   (97, 500, 8, 64, 2.0, 2), (640, 128, 64, 8, 3.5, 3)])
+def test_row_norm_brute_force(n, L, S, maxw, theta, seed):
+    rng = np.random.default_rng(100 + seed)
+    x = rng.integers(-40, 40, size=n)
+    x[n // 2:n // 2 + 4] += 150
+    x[: n // 5] += 30  # a step: per-block and per-row scales differ
+    got = oracle.search_row(x, 5, maxw, L, theta, S, row_norm=True)
+    want = brute_search_row(x.tolist(), 5, maxw, L, theta, S, row_norm=True)
+    assert as_tuples(oracle.sort_cands(got)) == want
+    assert len(want) > 0
+    _, _, mad = oracle.search_row(x, 5, maxw, L, theta, S, with_stats=True)
+    _, _, rmad = oracle.search_row(x, 5, maxw, L, theta, S, with_stats=True, row_norm=True)
+    assert np.all(rmad == rmad[0]) and not np.array_equal(mad, rmad)
+
+
+def test_row_norm_shift_and_scale_invariance():
+    # adding a constant moves every median by it; doubling doubles every sum
+    # and MAD exactly (binary floating point), so the S/N values are unchanged
+    rng = np.random.default_rng(17)
+    x = rng.integers(-500, 500, size=(3, 3000))
+    x[:, 1000:1010] += 3000
+    ref = oracle.search(x.astype(np.float32), 64, 700, 4.0, row_norm=True)
+    assert ref.size > 0
+    for y in (x + 12345, 2 * x, 2 * x - 77):
+        assert np.array_equal(oracle.search(y.astype(np.float32), 64, 700, 4.0, row_norm=True), ref)
+
+
+def test_row_norm_equals_block_norm_on_periodic_rows():
+    # a row repeating one 64-sample pattern: every window of whole blocks holds
+    # copies of the pattern, so each block's median and MAD are the pattern's,
+    # the residual's row median is 0 and its row MAD is the block MAD
+    rng = np.random.default_rng(23)
+    pat = rng.integers(-30, 30, size=64)
+    pat[17] += 400
+    x = np.tile(pat, 40)[None, :].astype(np.float32)
+    a, m, mad = oracle.search(x, 8, 64 * 5, 3.0, with_stats=True)
+    b, _, rmad = oracle.search(x, 8, 64 * 5, 3.0, with_stats=True, row_norm=True)
+    assert np.all(mad == mad[0, 0]) and np.array_equal(mad, rmad)
+    assert a.size > 0 and np.array_equal(a, b)
+
+
+def test_row_mad_closed_form():
+    # residual of a constant-baseline row {0, 1, ..., n-1} shifted: about its median
+    r = np.arange(11) - 3
+    assert oracle.row_mad(r) == 3  # lower median 2, deviations 0..8 -> sorted rank 5 is 3
+    assert oracle.row_mad(np.array([5, 5, 5, 9])) == 0
+    assert oracle.row_mad(np.array([1, -1])) == 0  # lower median -1: deviations {2, 0}
