@@ -149,6 +149,12 @@ int sps_search_plain(sps_plan* plan, const float* d_series, hipStream_t stream, 
                                      (Section II-B's moving baseline; the paper does not place the window).
                                      Plans and batches; a stream refuses a plan with 1 (its blocks would
                                      wait for lead samples of the next gulp). */
+#define SPS_ATTR_NORM 8           /* noise scale, part of the arithmetic: 0 (default) the block's MAD_k;
+                                     1 one scale per DM row, MAD_row = lower median of |r_t - c| over the
+                                     whole row, r_t = x_t - m_{t/64} and c the lower median of r (Section
+                                     II-B's normalisation read as one scale per trial and chunk). Every
+                                     block of the row then reports and uses MAD_row. Plans and batches; a
+                                     stream refuses a plan with 1 (the row is not complete in one gulp). */
 #define SPS_ATTR_NBLOCKS 16       /* read-only: ceil(nsamp / 64) */
 #define SPS_ATTR_NWIDTHS 17       /* read-only: number of boxcar widths */
 #define SPS_ATTR_BLOCK_STRIDE 18  /* read-only: S = SPS_BLOCK_STRIDE, part of the arithmetic (never tuned) */
@@ -182,7 +188,8 @@ int sps_timing_read(sps_plan* plan, double* ms_out, int64_t* nsearch);
  * sps_stream_create: `plan` gives the gulp shape (ndm x nsamp, nsamp a
  *   multiple of 64) and parameters; it must outlive the stream, and the
  *   stream must not run concurrently with another use of the plan. A plan
- *   with SPS_ATTR_WINDOW = 1 is refused (SPS_ERR_INVALID_ARG).
+ *   with SPS_ATTR_WINDOW = 1 or SPS_ATTR_NORM = 1 is refused
+ *   (SPS_ERR_INVALID_ARG).
  * sps_stream_push: search one gulp (device FP32 [ndm][nsamp]); candidates are
  *   those whose runs ended during this gulp, with `sample` relative to the
  *   gulp's first sample (negative: the boxcar started in an earlier gulp).
@@ -234,8 +241,8 @@ void sps_stream_destroy(sps_stream* s);
  *   SPS_ERR_INVALID_ARG (any item invalid: nothing enqueued), SPS_ERR_OOM,
  *   SPS_ERR_HIP.
  * sps_batch_set: tuning attributes SPS_ATTR_STATS_SEG, SPS_ATTR_DETECT_SEG,
- *   SPS_ATTR_HIST_BINS, and SPS_ATTR_WINDOW (same meaning as for plans; apply
- *   to every item).
+ *   SPS_ATTR_HIST_BINS, SPS_ATTR_WINDOW and SPS_ATTR_NORM (same meaning as for
+ *   plans; apply to every item).
  * sps_batch_destroy: waits for the context's work and frees it (NULL-safe).
  */
 typedef struct {

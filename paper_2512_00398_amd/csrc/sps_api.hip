@@ -23,6 +23,7 @@ struct sps_plan {
   int32_t detect_seg;  // samples per detection segment, 0 = auto
   int32_t hist_bins;   // 4096 or 16384
   int32_t window;      // SPS_ATTR_WINDOW: 0 trailing, 1 centred (changes results)
+  int32_t norm;        // SPS_ATTR_NORM: 0 per-block MAD, 1 one MAD per row (changes results)
   int device;
   // scratch owned by the plan
   int32_t* d_med;
@@ -369,6 +370,10 @@ int sps_plan_set(sps_plan* p, int attr, int64_t v) {
       if ((v != 0 && v != 1) || !window_fits(p->nsamp, p->baseline_len, (int)v)) return fail(SPS_ERR_INVALID_ARG);
       p->window = (int32_t)v;
       return ok();
+    case SPS_ATTR_NORM:
+      if (v != 0 && v != 1) return fail(SPS_ERR_INVALID_ARG);
+      p->norm = (int32_t)v;
+      return ok();
     default:
       return fail(SPS_ERR_INVALID_ARG);
   }
@@ -384,6 +389,7 @@ int sps_plan_get(const sps_plan* p, int attr, int64_t* v) {
     case SPS_ATTR_TIMING: *v = p->timing; break;
     case SPS_ATTR_VALIDATE: *v = p->validate; break;
     case SPS_ATTR_WINDOW: *v = p->window; break;
+    case SPS_ATTR_NORM: *v = p->norm; break;
     case SPS_ATTR_NBLOCKS: *v = p->nblocks; break;
     case SPS_ATTR_BLOCK_STRIDE: *v = sps::kStride; break;
     case SPS_ATTR_NWIDTHS: *v = p->nw; break;
@@ -420,6 +426,10 @@ static int launch_stats(sps_plan* p, const float* d_series, hipStream_t stream, 
   a.med = d_median;
   a.mad = d_mad;
   if (sps::launch_block_stats(a, p->hist_bins, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  if (p->norm == 1) {
+    const sps::RowMadArgs r{d_series, p->nsamp, p->nsamp, p->nblocks, p->ndm, d_median, d_mad};
+    if (sps::launch_row_mad(r, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  }
   return ok();
 }
 
@@ -679,6 +689,7 @@ int sps_stream_create(sps_plan* p, sps_stream** out) {
   *out = nullptr;
   if (p->nsamp % sps::kStride != 0) return fail(SPS_ERR_INVALID_ARG);  // gulps must hold whole blocks
   if (p->window != 0) return fail(SPS_ERR_INVALID_ARG);  // a centred window would wait for the next gulp
+  if (p->norm != 0) return fail(SPS_ERR_INVALID_ARG);    // a row scale needs the whole row
   sps_stream* s = new (std::nothrow) sps_stream;
   if (!s) return fail(SPS_ERR_OOM);
   std::memset(s, 0, sizeof(*s));
@@ -993,6 +1004,7 @@ struct sps_batch {
   int device;
   int32_t stats_seg, detect_seg, hist_bins;
   int32_t window;      // SPS_ATTR_WINDOW for every item
+  int32_t norm;        // SPS_ATTR_NORM for every item
   int32_t* d_ms;       // medians then MADs of every item
   int64_t ms_cap;      // int32 records
   sps::RunSum* d_frag;
@@ -1025,6 +1037,15 @@ bool item_valid(const sps_batch_item& it) {
 }
 
 size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// Row scales of a batch (SPS_ATTR_NORM = 1): one launch per item.
+hipError_t launch_row_mads(const std::vector<sps::RowMadArgs>& v, hipStream_t s) {
+  for (const sps::RowMadArgs& r : v) {
+    const hipError_t e = sps::launch_row_mad(r, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 template <class T>
 int grow(T** p, int64_t* cap, int64_t need) {
@@ -1082,6 +1103,10 @@ int sps_batch_set(sps_batch* b, int attr, int64_t v) {
     case SPS_ATTR_WINDOW:
       if (v != 0 && v != 1) return fail(SPS_ERR_INVALID_ARG);
       b->window = (int32_t)v;
+      return ok();
+    case SPS_ATTR_NORM:
+      if (v != 0 && v != 1) return fail(SPS_ERR_INVALID_ARG);
+      b->norm = (int32_t)v;
       return ok();
     default:
       return fail(SPS_ERR_INVALID_ARG);
@@ -1222,6 +1247,7 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
     return cx > cy;
   });
   int32_t acc = 0;
+  std::vector<sps::RowMadArgs> row_mads;
   for (int32_t k = 0; k < n; ++k) {
     const BatchShape& s = ord[(size_t)k];
     const sps_batch_item& it = items[s.idx];
@@ -1241,6 +1267,7 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
     a.tmin = nullptr;
     a.med = b->d_ms + s.ms_off;
     a.mad = b->d_ms + s.ms_off + (int64_t)it.ndm * s.nblocks;
+    if (b->norm == 1) row_mads.push_back(sps::RowMadArgs{a.x, a.ld, a.N, a.nblocks, it.ndm, a.med, a.mad});
     so[k] = acc;
     acc += a.nchains;
   }
@@ -1306,6 +1333,7 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
   const int gd = (int)std::min<int64_t>(b->grid_detect[all13 ? 0 : 1], bd.total);
   if (sps::launch_batch_zero(reinterpret_cast<uint32_t* const*>(d + off_np), n, counters, stream) != hipSuccess ||
       sps::launch_block_stats_batch(bs, b->hist_bins, gs, stream) != hipSuccess ||
+      launch_row_mads(row_mads, stream) != hipSuccess ||
       sps::launch_detect_batch(bd, all13 ? 13 : 0, gd, stream) != hipSuccess ||
       sps::launch_fixup_batch(bd, reinterpret_cast<const int32_t*>(d + off_fo), fo[n], stream) != hipSuccess ||
       hipEventRecord(b->done, stream) != hipSuccess) {

@@ -58,6 +58,18 @@ struct StatsArgs {
   int32_t* mad;
 };
 
+// One scale per row: MAD of the row's residual (against med) about its
+// lower median, written to every block of mad.
+struct RowMadArgs {
+  const float* x;
+  int64_t ld;          // row stride of x in samples
+  int32_t N;           // row length
+  int32_t nblocks;     // row stride of med / mad
+  int32_t rows;
+  const int32_t* med;  // [rows][nblocks]
+  int32_t* mad;        // [rows][nblocks], overwritten
+};
+
 struct DetectArgs {
   const float* x;
   int64_t ld;
@@ -170,6 +182,7 @@ hipError_t launch_block_stats(const StatsArgs& a, int hist_bins, hipStream_t s);
 hipError_t launch_detect(const DetectArgs& a, hipStream_t s);
 hipError_t launch_fixup(const DetectArgs& a, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
+hipError_t launch_row_mad(const RowMadArgs& a, hipStream_t s);
 hipError_t launch_validate(const float* x, int64_t n, float bound, uint32_t* bad, hipStream_t s);
 hipError_t launch_stream_fold(const StreamArgs& a, hipStream_t s);
 hipError_t launch_stream_advance(const StreamArgs& a, hipStream_t s);
