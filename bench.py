@@ -38,8 +38,8 @@ KERNEL_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md
-    "detect": ("d4c390cc81980d89", (2237764 * 2 + 170195) * 1024),
-    "block_stats": ("29c6a4c7e45bd3fa", (4349690 * 2 + 137215) * 1024),
+    "detect": ("e5b2798e703d9c6e", (2237778 * 2 + 170181) * 1024),
+    "block_stats": ("3060eeb6e072252e", (4349622 * 2 + 138194) * 1024),
 }
 
 
@@ -65,25 +65,25 @@ def log(*a):
 
 def _oracle_row(args):
     """CPU-baseline worker: the oracle on one row of the workload (timed inside)."""
-    cfg_index, row = args
+    cfg_index, row, centred, row_norm = args
     import numpy as np  # noqa: F401
     import oracle
     import synth
     b = synth.config(cfg_index)["blocks"][0]
     x = synth.generate(b, rows=[row], nthreads=1)
     t0 = time.time()
-    c = oracle.search(x, b.max_width, b.baseline_len, b.snr_thresh)
+    c = oracle.search(x, b.max_width, b.baseline_len, b.snr_thresh, centered=centred, row_norm=row_norm)
     t1 = time.time()
     return t0, t1, int(c.size), b.nsamp
 
 
-def cpu_baseline(cfg_index: int, nrows: int):
+def cpu_baseline(cfg_index: int, nrows: int, centred: bool = False, row_norm: bool = False):
     procs = max(1, min(16, os.cpu_count() or 1, nrows))
     ndm = __import__("synth").config(cfg_index)["blocks"][0].ndm
     rows = [int(r * (ndm - 1) / max(1, nrows - 1)) for r in range(nrows)]
     ctx = mp.get_context("spawn")
     with ctx.Pool(procs) as pool:
-        res = pool.map(_oracle_row, [(cfg_index, r) for r in rows])
+        res = pool.map(_oracle_row, [(cfg_index, r, centred, row_norm) for r in rows])
     span = max(r[1] for r in res) - min(r[0] for r in res)
     samples = sum(r[3] for r in res)
     return {"value": samples / span, "unit": "DM-trial-samples/s", "cores": procs, "kind": "oracle",
@@ -330,6 +330,10 @@ def main():
                     help="rows timed for the per-DM-trial loop of the plain path (0: skip)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the plan's speed-only attributes on the input first (untimed; cached as JSON)")
+    ap.add_argument("--window", default="trailing", choices=["trailing", "centred"],
+                    help="baseline window placement (SPS_ATTR_WINDOW)")
+    ap.add_argument("--norm", default="block", choices=["block", "row"],
+                    help="noise scale: per-block MAD or one MAD per DM row (SPS_ATTR_NORM)")
     ap.add_argument("--mode", default="search", choices=["search", "copy"],
                     help="copy: time a plain device-to-device copy of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -364,7 +368,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on %d rows" % args.cpu_rows)
-        cpu = cpu_baseline(args.config, args.cpu_rows)
+        cpu = cpu_baseline(args.config, args.cpu_rows, args.window == "centred", args.norm == "row")
         log("cpu baseline: %.3g samples/s on %d cores" % (cpu["value"], cpu["cores"]))
 
     import numpy as np
@@ -380,6 +384,10 @@ def main():
     del x
     stream = torch.cuda.current_stream()
     plan = sps.Plan(b.ndm, b.nsamp, b.max_width, b.baseline_len, b.snr_thresh)
+    variant = {sps.ATTR_WINDOW: int(args.window == "centred"), sps.ATTR_NORM: int(args.norm == "row")}
+    for attr, v in variant.items():
+        plan.set(attr, v)
+    default_variant = not any(variant.values())
     tuned = None
     if args.autotune:
         from paper_2512_00398_amd import autotune
@@ -425,6 +433,8 @@ def main():
     if not args.no_plain and args.per_dm_rows > 0:
         rows = min(args.per_dm_rows, b.ndm)
         p1 = sps.Plan(1, b.nsamp, b.max_width, b.baseline_len, b.snr_thresh)
+        for attr, v in variant.items():
+            p1.set(attr, v)
         c1, n1 = p1.alloc_cands()
         p1.search(xd[0:1], c1, n1, stream=stream, plain=True)
         torch.cuda.synchronize()
@@ -464,6 +474,8 @@ def main():
     avg = {k: v / max(1, nsearch) for k, v in stages.items()}
     # algorithmic bytes per launch of each kernel
     bytes_stats = b.ndm * (4.0 * b.nsamp + 8.0 * nblocks)
+    if args.norm == "row":
+        bytes_stats += b.ndm * 8.0 * b.nsamp  # the row scale's two passes over the row
     bytes_detect = b.ndm * (4.0 * b.nsamp + 8.0 * nblocks) + 16.0 * n
     dom = "block_stats" if avg["block_stats"] >= avg["detect"] else "detect"
     dom_bytes = bytes_stats if dom == "block_stats" else bytes_detect
@@ -481,12 +493,13 @@ def main():
         "vs_baseline": None,
         "dtype": "i32",
         "data": "synthetic",
-        "config": {"workload": "%s: ndm=%d nsamp=%d widths=1..%d baseline=%d theta=%g" %
-                               (cfg["name"], b.ndm, b.nsamp, b.max_width, b.baseline_len, b.snr_thresh),
+        "config": {"workload": "%s: ndm=%d nsamp=%d widths=1..%d baseline=%d theta=%g%s" %
+                               (cfg["name"], b.ndm, b.nsamp, b.max_width, b.baseline_len, b.snr_thresh,
+                                "" if default_variant else " window=%s norm=%s" % (args.window, args.norm)),
                    "input": "f32 integer-valued, HBM-resident", "snr": "f64 decision, f32 output"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom) if args.config == 2 else None,
+                     "traffic": measured_traffic(dom) if args.config == 2 and default_variant else None,
                      "algorithmic_bytes": dom_bytes},
         "path_hbm_frac": 4.0 * value / 1e9 / HBM_PEAK_GBS,
         "stages_ms": {k: round(v, 4) for k, v in avg.items() if k != "plain"},
