@@ -1332,7 +1332,7 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
   const int gs = (int)std::min<int64_t>(b->grid_stats[bins], (bs.total + wpg - 1) / wpg);
   const int gd = (int)std::min<int64_t>(b->grid_detect[all13 ? 0 : 1], bd.total);
   if (sps::launch_batch_zero(reinterpret_cast<uint32_t* const*>(d + off_np), n, counters, stream) != hipSuccess ||
-      sps::launch_block_stats_batch(bs, b->hist_bins, gs, stream) != hipSuccess ||
+      sps::launch_block_stats_batch(bs, b->hist_bins, b->window == 1, gs, stream) != hipSuccess ||
       launch_row_mads(row_mads, stream) != hipSuccess ||
       sps::launch_detect_batch(bd, all13 ? 13 : 0, gd, stream) != hipSuccess ||
       sps::launch_fixup_batch(bd, reinterpret_cast<const int32_t*>(d + off_fo), fo[n], stream) != hipSuccess ||

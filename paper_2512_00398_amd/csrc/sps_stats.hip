@@ -374,15 +374,16 @@ __device__ __forceinline__ void chain_step(Chain<NB, VIRT>& c, int lo, int hi, b
 
 // WPG chains (waves) per workgroup; LDS = WPG * NB * 2 bytes. Blocks
 // [kb_first, nblocks) of every row are computed; windows never reach below
-// the device value *tmin (the first sample of a stream).
-template <int NB, bool VIRT>
+// the device value *tmin (the first sample of a stream). LEAD: the window
+// reaches a.lead samples past its block (false: trailing, offset compiled out).
+template <int NB, bool VIRT, bool LEAD>
 __device__ __forceinline__ void stats_chain(const StatsArgs& a, const int chain, uint32_t* H, const int lane) {
   const int row = chain / a.nseg;
   const int seg = chain - row * a.nseg;
   // segment 0 has head_blocks blocks, the others seg_blocks each
   const int kb0 = a.kb_first + (seg == 0 ? 0 : a.head_blocks + (seg - 1) * a.seg_blocks);
   const int kb1 = min(a.nblocks, seg == 0 ? a.kb_first + a.head_blocks : kb0 + a.seg_blocks);
-  const int N = a.N, L = a.L, lead = a.lead;
+  const int N = a.N, L = a.L, lead = LEAD ? a.lead : 0;
   const int t0 = a.tmin ? *a.tmin : 0;
   Chain<NB, VIRT> c;
   c.H = H;
@@ -439,7 +440,7 @@ __device__ __forceinline__ void stats_chain(const StatsArgs& a, const int chain,
   }
 }
 
-template <int NB, int WPG, bool VIRT>
+template <int NB, int WPG, bool VIRT, bool LEAD>
 __global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
   __shared__ uint32_t hist[WPG][NB / 2];
   // wave index made uniform: the chain's bookkeeping then runs on the scalar
@@ -447,12 +448,12 @@ __global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
   const int wave = readfirst(threadIdx.x >> 6);
   const int chain = blockIdx.x * WPG + wave;
   if (chain >= a.nchains) return;  // whole wave leaves; no block barriers are used
-  stats_chain<NB, VIRT>(a, chain, hist[wave], lane_id());
+  stats_chain<NB, VIRT, LEAD>(a, chain, hist[wave], lane_id());
 }
 
 // Persistent form over a batch: every wave takes chains from the queue on its
 // own (no block barriers) until the counter passes the total.
-template <int NB, int WPG>
+template <int NB, int WPG, bool LEAD>
 __global__ __launch_bounds__(64 * WPG) void k_block_stats_batch(BatchStats B) {
   __shared__ uint32_t hist[WPG][NB / 2];
   const int wave = threadIdx.x >> 6;
@@ -464,7 +465,7 @@ __global__ __launch_bounds__(64 * WPG) void k_block_stats_batch(BatchStats B) {
     if (task >= B.total) break;
     int it = 0;
     while (it + 1 < B.nitems && B.offs[it + 1] <= task) ++it;
-    stats_chain<NB, false>(B.items[it], task - B.offs[it], hist[wave], lane);
+    stats_chain<NB, false, LEAD>(B.items[it], task - B.offs[it], hist[wave], lane);
   }
 }
 
@@ -473,20 +474,31 @@ __global__ __launch_bounds__(64 * WPG) void k_block_stats_batch(BatchStats B) {
 hipError_t launch_block_stats(const StatsArgs& a, int hist_bins, hipStream_t s) {
   if (a.nchains <= 0) return hipSuccess;
   const bool virt = a.Hx > 0;
+  if (virt && a.lead != 0) return hipErrorInvalidValue;  // streams use the trailing window only
+  const bool lead = a.lead != 0;
   if (hist_bins == 16384) {
-    if (virt) hipLaunchKernelGGL((k_block_stats<16384, 2, true>), dim3((a.nchains + 1) / 2), dim3(128), 0, s, a);
-    else hipLaunchKernelGGL((k_block_stats<16384, 2, false>), dim3((a.nchains + 1) / 2), dim3(128), 0, s, a);
+    const dim3 g((a.nchains + 1) / 2), b(128);
+    if (virt) hipLaunchKernelGGL((k_block_stats<16384, 2, true, false>), g, b, 0, s, a);
+    else if (lead) hipLaunchKernelGGL((k_block_stats<16384, 2, false, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_block_stats<16384, 2, false, false>), g, b, 0, s, a);
   } else {
-    if (virt) hipLaunchKernelGGL((k_block_stats<4096, 4, true>), dim3((a.nchains + 3) / 4), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_block_stats<4096, 4, false>), dim3((a.nchains + 3) / 4), dim3(256), 0, s, a);
+    const dim3 g((a.nchains + 3) / 4), b(256);
+    if (virt) hipLaunchKernelGGL((k_block_stats<4096, 4, true, false>), g, b, 0, s, a);
+    else if (lead) hipLaunchKernelGGL((k_block_stats<4096, 4, false, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_block_stats<4096, 4, false, false>), g, b, 0, s, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_block_stats_batch(const BatchStats& b, int hist_bins, int grid, hipStream_t s) {
+hipError_t launch_block_stats_batch(const BatchStats& b, int hist_bins, bool lead, int grid, hipStream_t s) {
   if (b.total <= 0) return hipSuccess;
-  if (hist_bins == 16384) hipLaunchKernelGGL((k_block_stats_batch<16384, 2>), dim3(grid), dim3(128), 0, s, b);
-  else hipLaunchKernelGGL((k_block_stats_batch<4096, 4>), dim3(grid), dim3(256), 0, s, b);
+  if (hist_bins == 16384) {
+    if (lead) hipLaunchKernelGGL((k_block_stats_batch<16384, 2, true>), dim3(grid), dim3(128), 0, s, b);
+    else hipLaunchKernelGGL((k_block_stats_batch<16384, 2, false>), dim3(grid), dim3(128), 0, s, b);
+  } else {
+    if (lead) hipLaunchKernelGGL((k_block_stats_batch<4096, 4, true>), dim3(grid), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_block_stats_batch<4096, 4, false>), dim3(grid), dim3(256), 0, s, b);
+  }
   return hipGetLastError();
 }
 
@@ -494,9 +506,10 @@ int block_stats_batch_grid(int hist_bins) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  // resident workgroups are limited by LDS, the same for both window placements
   hipError_t e = hist_bins == 16384
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_block_stats_batch<16384, 2>, 128, 0)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_block_stats_batch<4096, 4>, 256, 0);
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_block_stats_batch<16384, 2, false>, 128, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_block_stats_batch<4096, 4, false>, 256, 0);
   if (e != hipSuccess) return 0;
   return cus * (per > 0 ? per : 1);
 }
