@@ -5,14 +5,16 @@
 // MAD_row = the lower median of |r_t - c|; every block of the row then takes
 // MAD_row as its scale. Exact integer order statistics.
 //
-// One 1024-thread workgroup per row. Each order statistic is an exact select
-// of rank (N-1)/2: a first pass histograms a 4096-value window in LDS (around
-// 0 for the residual, from 0 for the deviations, where these statistics sit
-// for any baseline-removed row) and counts the values below it; if the rank
-// falls inside, a block scan of the histogram gives the answer. Otherwise a
-// radix select (digits of 12, 12 and 8 bits, most significant first) over
-// the same keys finds it. Each pass reads the row once, coalesced; HBM
-// traffic is 2 x 4 B per sample in the common case.
+// One 1024-thread workgroup per row. One pass histograms the residuals in a
+// 4096-value LDS window around 0 (where the median of a baseline-removed row
+// sits) and counts those below it. When c falls inside the window, the same
+// histogram, prefix-summed, gives #{|r - c| <= d} = P(c + d) - P(c - d - 1)
+// for every d with [c - d, c + d] inside the window, and MAD_row is the
+// smallest d whose count exceeds the rank: one read of the row. Otherwise
+// each statistic is an exact select of rank (N-1)/2 of its own: the window
+// pass (from 0 for the deviations), then, if the rank lies outside, a radix
+// select (digits of 12, 12 and 8 bits, most significant first). HBM traffic
+// in the common case: 4 B per sample.
 #include <hip/hip_runtime.h>
 
 #include "sps_internal.h"
@@ -78,6 +80,25 @@ __device__ int find_bin(RowShared& S, uint32_t rho) {
   return total;
 }
 
+// H[b] <- H[0] + ... + H[b] (every thread owns 4 bins).
+__device__ void prefix_hist(RowShared& S) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6, t = threadIdx.x;
+  const uint32_t h0 = S.H[4 * t], h1 = S.H[4 * t + 1], h2 = S.H[4 * t + 2], h3 = S.H[4 * t + 3];
+  const int c = (int)(h0 + h1 + h2 + h3);
+  const int incl = wave_scan_incl(c);
+  if (lane == 63) S.part[wave] = incl;
+  __syncthreads();
+  int base = 0;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) base += k < wave ? S.part[k] : 0;
+  const uint32_t ex = (uint32_t)(base + incl - c);
+  S.H[4 * t] = ex + h0;
+  S.H[4 * t + 1] = ex + h0 + h1;
+  S.H[4 * t + 2] = ex + h0 + h1 + h2;
+  S.H[4 * t + 3] = ex + h0 + h1 + h2 + h3;
+  __syncthreads();
+}
+
 __device__ __forceinline__ void clear_hist(RowShared& S) {
   for (int b = threadIdx.x; b < kBins; b += kThreads) S.H[b] = 0;
   __syncthreads();
@@ -129,12 +150,62 @@ __global__ __launch_bounds__(kThreads) void k_row_mad(RowMadArgs a) {
   const int32_t* m = a.med + (int64_t)row * a.nblocks;
   const int n = a.N;
   const uint32_t rho = (uint32_t)((n - 1) / 2);
-  // residual keys: two's complement with the sign bit flipped orders as unsigned
-  const uint32_t kc = select_rank([&](int i) { return (uint32_t)resid(x, m, i) ^ 0x80000000u; }, n, rho,
-                                  0x80000000u - kBins / 2, S);
-  const int c = (int)(kc ^ 0x80000000u);
-  const uint32_t d = select_rank([&](int i) { const int v = resid(x, m, i) - c; return (uint32_t)(v < 0 ? -v : v); },
-                                 n, rho, 0u, S);
+  constexpr int kHalf = kBins / 2;
+
+  // residual histogram over [-2048, 2048), 4 consecutive samples per thread
+  clear_hist(S);
+  int below = 0;
+  auto add = [&](int r) {
+    const uint32_t b = (uint32_t)(r + kHalf);
+    if (b < (uint32_t)kBins) atomicAdd(&S.H[b], 1u);
+    else below += r < -kHalf ? 1 : 0;
+  };
+  const bool vec = (reinterpret_cast<uintptr_t>(x) & 15u) == 0;
+  for (int i = 4 * (int)threadIdx.x; i < n; i += 4 * kThreads) {
+    const int mk = m[i >> 6];  // the 4 samples share one 64-sample block
+    if (vec && i + 3 < n) {
+      const float4 v = *reinterpret_cast<const float4*>(x + i);
+      add((int)v.x - mk);
+      add((int)v.y - mk);
+      add((int)v.z - mk);
+      add((int)v.w - mk);
+    } else {
+      for (int q = 0; q < 4; ++q)
+        if (i + q < n) add((int)x[i + q] - mk);
+    }
+  }
+  __syncthreads();
+  const uint32_t B = (uint32_t)block_sum(below, S);
+  int c = 0;
+  bool cwin = false;
+  if (rho >= B) {
+    find_bin(S, rho - B);
+    cwin = S.found < (uint32_t)kBins;
+    c = (int)S.found - kHalf;
+  }
+  uint32_t d = 0;
+  bool dwin = false;
+  if (cwin) {
+    // smallest d with #{|r - c| <= d} > rho, over the d whose interval stays in the window
+    prefix_hist(S);
+    const int cb = c + kHalf, dmax = min(cb, kBins - 1 - cb);
+    if (threadIdx.x == 0) S.found = kBins;
+    __syncthreads();
+    auto cnt = [&](int dd) { return S.H[cb + dd] - (cb - dd - 1 >= 0 ? S.H[cb - dd - 1] : 0u); };
+    for (int dd = threadIdx.x; dd <= dmax; dd += kThreads)
+      if (cnt(dd) > rho && (dd == 0 || cnt(dd - 1) <= rho)) S.found = (uint32_t)dd;
+    __syncthreads();
+    dwin = S.found < (uint32_t)kBins;
+    d = S.found;
+  } else {
+    // residual keys: two's complement with the sign bit flipped orders as unsigned
+    const uint32_t kc = select_rank([&](int i) { return (uint32_t)resid(x, m, i) ^ 0x80000000u; }, n, rho,
+                                    0x80000000u - kHalf, S);
+    c = (int)(kc ^ 0x80000000u);
+  }
+  if (!dwin)
+    d = select_rank([&](int i) { const int v = resid(x, m, i) - c; return (uint32_t)(v < 0 ? -v : v); }, n, rho, 0u,
+                    S);
   int32_t* out = a.mad + (int64_t)row * a.nblocks;
   for (int k = threadIdx.x; k < a.nblocks; k += kThreads) out[k] = (int32_t)d;
 }

@@ -75,6 +75,12 @@ def test_row_norm_edge_cases_and_plain_path():
     t = np.arange(20000, dtype=np.float64)
     x = np.stack([np.round(2000.0 * (t % 7000)), np.round(rng.uniform(-4e6, 4e6, size=t.size))]).astype(np.float32)
     check(x, 64, 900, 2.5, "ramp-wide")
+    # median inside the LDS window, MAD far outside it: 40% / 20% / 40% of the
+    # samples at -1e5 / 0 / +1e5 (the deviations take their own select)
+    lev = rng.choice(np.array([-1e5, 0.0, 1e5]), p=[0.4, 0.2, 0.4], size=(2, 12000))
+    x = (lev + np.round(rng.normal(0, 20, size=lev.shape))).astype(np.float32)
+    x[0, 5000:5004] += 6e5
+    check(x, 32, 2000, 2.0, "three-level")
     # heavy ties and steps
     x = rng.integers(0, 3, size=(2, 9000)).astype(np.float32)
     x[1, 3000:] += 20000
