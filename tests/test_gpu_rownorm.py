@@ -132,3 +132,31 @@ def test_row_norm_attribute_rules():
         p.set(m.ATTR_NORM, 1)
         with pytest.raises(m.SpsError):
             m.Stream(p)
+
+
+def test_row_norm_full_size_sampled_rows():
+    # the 1024 x 2^20 block in the launch configuration the benchmark times
+    # (bench.py --norm row); the oracle checks sampled rows
+    import torch
+    m = sps()
+    cfg = synth.config(2)["blocks"][0]
+    print("case c2 full size row_norm: generate", flush=True)
+    x = synth.generate(cfg)
+    xd = torch.from_numpy(x).cuda()
+    rows = [3, 512, 1022]
+    with m.Plan(cfg.ndm, cfg.nsamp, cfg.max_width, cfg.baseline_len, cfg.snr_thresh) as p:
+        p.set(m.ATTR_NORM, 1)
+        cands, ncand = p.alloc_cands()
+        p.search(xd, cands, ncand)
+        med, mad = p.block_stats(xd)
+        torch.cuda.synchronize()
+        got = m.cands_to_numpy(cands, ncand, p.max_cands)
+        med, mad = med.cpu().numpy(), mad.cpu().numpy()
+    print("case c2 row_norm: oracle on rows %s (%d gpu candidates)" % (rows, got.size), flush=True)
+    ref, rm, rmad = oracle.search(x, cfg.max_width, cfg.baseline_len, cfg.snr_thresh, rows=rows, with_stats=True,
+                                  row_norm=True)
+    assert np.array_equal(med[rows], rm) and np.array_equal(mad[rows], rmad)
+    assert all(np.all(mad[r] == mad[r, 0]) for r in range(cfg.ndm))
+    sel = np.isin(got["dm_idx"], rows)
+    assert compare_cands(got[sel], ref, cfg.snr_thresh, "c2-rownorm-rows") == 0
+    assert exact_equal(got[sel], ref)

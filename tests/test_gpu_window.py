@@ -133,3 +133,33 @@ def test_centred_window_attribute_rules():
         p.set(m.ATTR_WINDOW, 0)
         s = m.Stream(p)
         s.close()
+
+
+@pytest.mark.parametrize("row_norm", [False, True])
+def test_variants_full_size_sampled_rows(row_norm):
+    # the 1024 x 2^20 block in the launch configuration the benchmark times
+    # (bench.py --window centred [--norm row]); the oracle checks sampled rows
+    import torch
+    m = sps()
+    cfg = synth.config(2)["blocks"][0]
+    print("case c2 full size centred row_norm=%s: generate" % row_norm, flush=True)
+    x = synth.generate(cfg)
+    xd = torch.from_numpy(x).cuda()
+    rows = [0, 700, 1023]
+    with m.Plan(cfg.ndm, cfg.nsamp, cfg.max_width, cfg.baseline_len, cfg.snr_thresh) as p:
+        p.set(m.ATTR_WINDOW, 1)
+        p.set(m.ATTR_NORM, int(row_norm))
+        cands, ncand = p.alloc_cands()
+        p.search(xd, cands, ncand)
+        med, mad = p.block_stats(xd)
+        torch.cuda.synchronize()
+        got = m.cands_to_numpy(cands, ncand, p.max_cands)
+        med, mad = med.cpu().numpy(), mad.cpu().numpy()
+    print("case c2 centred: oracle on rows %s (%d gpu candidates)" % (rows, got.size), flush=True)
+    ref, rm, rmad = oracle.search(x, cfg.max_width, cfg.baseline_len, cfg.snr_thresh, rows=rows, with_stats=True,
+                                  centered=True, row_norm=row_norm)
+    assert np.array_equal(med[rows], rm) and np.array_equal(mad[rows], rmad)
+    sel = np.isin(got["dm_idx"], rows)
+    assert compare_cands(got[sel], ref, cfg.snr_thresh, "c2-centred-rows") == 0
+    assert exact_equal(got[sel], ref)
+    assert (got["sample"].astype(np.int64) + got["width"] <= cfg.nsamp).all()
