@@ -23,6 +23,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# 32-bit integer vector adds: 256 CUs x 64 lanes per clock x 2.4 GHz
+ALU_INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 # HBM bytes per launch on the default workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a
@@ -172,6 +174,86 @@ def bench_stream(args):
     print(json.dumps(out))
 
 
+def bench_dedisp(args):
+    """Incoherent dedispersion on the device, the producer of the search's
+    input: a seeded 8-bit filterbank of 1024 channels over 1050-1450 MHz at
+    49.152 us (FAST-like L band), 1024 trial DMs over 0-1000 pc cm^-3, output
+    chunks of 2^18 samples (the paper's 256K-sample chunks), channel-major and
+    HBM-resident before the timed region. Also times dedispersion followed by
+    the search of its output (the device-resident pipeline)."""
+    import numpy as np
+    import torch
+    from synth import filterbank as fb
+    from paper_2512_00398_amd import sps
+
+    nchan, ndm, nout, tsamp = 1024, 1024, 1 << 18, 49.152e-6
+    f, fref = fb.band(nchan)
+    dms = np.linspace(0, 1000, ndm).astype(np.float32)
+    tab = sps.dedisp_delays(f, fref, tsamp, dms)
+    nin = nout + int(tab.max())
+    log("generate filterbank %d x %d" % (nchan, nin))
+    rng = np.random.default_rng(77)
+    picks = rng.integers(0, ndm, size=24)
+    pulses = [(int(rng.integers(0, nout - 4096)), int(2 ** rng.integers(0, 9)), int(rng.integers(3, 30)))
+              for _ in picks]
+    fil = fb.filterbank(nchan, nin, seed=77, pulses=pulses, tracks=tab[picks])
+    fd = torch.from_numpy(fil).cuda()
+    stream = torch.cuda.current_stream()
+    k = sps.Dedisperser(nchan, nin, tab)
+    out = k.alloc_out()
+    for _ in range(args.warmup):
+        k.run(fd, out, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        k.run(fd, out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms = e0.elapsed_time(e1) / args.steps
+    ms = (t1 - t0) * 1e3 / args.steps
+    # the pipeline: dedispersion, then the search of its output
+    plan = sps.Plan(ndm, nout, 4096, 16384, 6.0)
+    cands, ncand = plan.alloc_cands()
+    k.run(fd, out, stream=stream)
+    plan.search(out, cands, ncand, stream=stream)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for _ in range(args.steps):
+        k.run(fd, out, stream=stream)
+        plan.search(out, cands, ncand, stream=stream)
+    torch.cuda.synchronize()
+    pipe_ms = (time.perf_counter() - tp0) * 1e3 / args.steps
+    n = int(ncand.item())
+    plan.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import dedisp_oracle as dd
+        rows = 8
+        c0 = time.perf_counter()
+        dd.dedisperse(fil, tab[:: ndm // rows][:rows].astype(np.int64))
+        cs = time.perf_counter() - c0
+        cpu = {"value": rows * nout / cs, "unit": "DM-trial-samples/s", "cores": 1, "kind": "oracle",
+               "sample": "%d of %d trial DMs, full %d-channel rows of %d samples, one process" % (rows, ndm, nchan, nout),
+               "seconds": round(cs, 3)}
+    k.close()
+    adds = float(ndm) * nchan * nout
+    achieved = adds / (kms * 1e-3) / 1e12
+    peak = ALU_INT32_PEAK_TOPS
+    print(json.dumps({
+        "metric": "DM-trial-samples/s", "value": ndm * nout / (ms * 1e-3), "unit": "DM-trial-samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8->i32", "data": "synthetic",
+        "config": {"workload": "dedisp: 1024 channels 1050-1450 MHz, tsamp 49.152 us, 1024 trial DMs 0-1000, "
+                               "%d output samples (%d input)" % (nout, nin)},
+        "roofline": {"bound": "alu", "kernel": "dedisp", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "algorithmic_ops": adds, "algorithmic_bytes": float(nchan) * nin + 4.0 * ndm * nout},
+        "kernel_ms": kms, "pipeline_ms_per_chunk": pipe_ms, "pipeline_candidates": n, "cpu_baseline": cpu}))
+
+
 def bench_batch(args):
     """Many-file workload: one batched search (persistent launch per stage)
     against a loop of single-block searches over the same resident files."""
@@ -313,10 +395,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5, 6],
                     help="1 small block, 2 single large block (default), 3 streaming 8 gulps through captured "
                          "HIP graphs, 4 batch of 32 files, "
-                         "5 serving 16 beams (literal arrival rate, then a time-compressed sweep)")
+                         "5 serving 16 beams (literal arrival rate, then a time-compressed sweep), "
+                         "6 incoherent dedispersion of a 1024-channel filterbank (and the search of its output)")
     ap.add_argument("--serve-horizon", type=float, default=20.0,
                     help="seconds of literal-rate arrivals served in --config 5")
     ap.add_argument("--serve-slots", type=int, default=8, help="gulps in flight at most in --config 5")
@@ -364,6 +447,8 @@ def main():
         return bench_batch(args)
     if args.config == 5:
         return bench_serve(args)
+    if args.config == 6:
+        return bench_dedisp(args)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -318,6 +318,45 @@ int sps_cluster_run(sps_clusterer* k, const sps_cand* d_cands, uint32_t n, int32
                     int32_t width_tol, hipStream_t stream, sps_cluster_rec* d_out, uint32_t* d_nout);
 void sps_cluster_destroy(sps_clusterer* k);
 
+/* ---- Incoherent dedispersion (Heimdall++ Section II-B, "Incoherent
+ * Dedispersion", the dispersion measure of Eq. 1, and the dedispersion step
+ * of Algorithm 1): the producer of the block sps_search consumes, on the
+ * device, from an 8-bit filterbank.
+ *
+ * sps_dedisp_delays (host only, no device work): the cold-plasma delay of
+ *   every channel at every trial DM, in samples,
+ *     delays[d*nchan + f] = floor(k_DM * dms[d] * (freqs_mhz[f]^-2 - f_ref_mhz^-2) / tsamp_s + 0.5),
+ *   k_DM = 4.148808e3 MHz^2 pc^-1 cm^3 s, evaluated in double precision in
+ *   that order (dms converted from float). Channel frequencies in MHz, each
+ *   in (0, f_ref_mhz]; DMs >= 0 (pc cm^-3); tsamp_s > 0. `delays` is a host
+ *   array of ndm * nchan int32 owned by the caller. SPS_ERR_INVALID_ARG for
+ *   bad sizes or values or a delay beyond INT32_MAX; SPS_OK otherwise.
+ * sps_dedisp_create: copies a host delay table [ndm][nchan] (int32, every
+ *   entry >= 0; any table, not only the one above) to the device. nchan in
+ *   [1, 65536]; nsamp_in in [1, INT32_MAX - 8192]; the largest delay must be
+ *   below nsamp_in. The output row length is nsamp_out = nsamp_in - largest
+ *   delay. NULL on error (sps_last_error: SPS_ERR_INVALID_ARG, SPS_ERR_OOM,
+ *   SPS_ERR_HIP). Synchronous.
+ * sps_dedisp_nsamp_out: nsamp_out (-1 and SPS_ERR_INVALID_ARG for NULL).
+ * sps_dedisp_run: d_fil is a device uint8 filterbank, channel-major
+ *   [nchan][nsamp_in] (row stride nsamp_in bytes), 4-byte aligned, read
+ *   only; d_out is a device FP32 [ndm][nsamp_out] array (row stride
+ *   nsamp_out), overwritten with
+ *     out[d][t] = sum_f fil[f][t + delays[d][f]],  0 <= t < nsamp_out,
+ *   exact integers (below 2^24 for nchan <= 65793, the domain sps_search
+ *   accepts). Asynchronous on `stream`; SPS_ERR_INVALID_ARG (NULL or
+ *   misaligned pointers), SPS_ERR_HIP (launch failure).
+ * sps_dedisp_destroy: waits for the device and frees the object (NULL-safe).
+ */
+typedef struct sps_dedisp sps_dedisp;
+
+int sps_dedisp_delays(int32_t nchan, const double* freqs_mhz, double f_ref_mhz, double tsamp_s, int32_t ndm,
+                      const float* dms, int32_t* delays);
+sps_dedisp* sps_dedisp_create(int32_t nchan, int64_t nsamp_in, int32_t ndm, const int32_t* delays);
+int64_t sps_dedisp_nsamp_out(const sps_dedisp* k);
+int sps_dedisp_run(sps_dedisp* k, const uint8_t* d_fil, hipStream_t stream, float* d_out);
+void sps_dedisp_destroy(sps_dedisp* k);
+
 /* Last error code of the calling thread, and a static text for a code. */
 int sps_last_error(void);
 const char* sps_error_string(int code);

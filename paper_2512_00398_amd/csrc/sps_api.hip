@@ -1424,3 +1424,155 @@ void sps_cluster_destroy(sps_clusterer* k) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- dedispersion
+
+struct sps_dedisp {
+  int32_t nchan, ndm, ndm_pad, dd;
+  int64_t nsamp_in, nsamp_out;
+  int32_t* d_delay;  // [nchan][ndm_pad]
+};
+
+namespace {
+
+constexpr double kDispersionConst = 4.148808e3;  // MHz^2 pc^-1 cm^3 s
+
+// Largest spread of the delays of `dd` consecutive trials in any channel.
+int64_t delay_spread(const std::vector<int32_t>& dt, int32_t nchan, int32_t ndm_pad, int32_t dd) {
+  int64_t spread = 0;
+  for (int32_t f = 0; f < nchan; ++f)
+    for (int32_t g = 0; g < ndm_pad; g += dd) {
+      const int32_t* p = &dt[(size_t)f * ndm_pad + g];
+      int32_t lo = p[0], hi = p[0];
+      for (int32_t j = 1; j < dd; ++j) {
+        lo = std::min(lo, p[j]);
+        hi = std::max(hi, p[j]);
+      }
+      spread = std::max<int64_t>(spread, (int64_t)hi - lo);
+    }
+  return spread;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sps_dedisp_delays(int32_t nchan, const double* freqs_mhz, double f_ref_mhz, double tsamp_s, int32_t ndm,
+                      const float* dms, int32_t* delays) {
+  if (nchan < 1 || ndm < 1 || !freqs_mhz || !dms || !delays || !(tsamp_s > 0.0) || !std::isfinite(tsamp_s) ||
+      !(f_ref_mhz > 0.0) || !std::isfinite(f_ref_mhz))
+    return fail(SPS_ERR_INVALID_ARG);
+  for (int32_t f = 0; f < nchan; ++f)
+    if (!(freqs_mhz[f] > 0.0) || !(freqs_mhz[f] <= f_ref_mhz)) return fail(SPS_ERR_INVALID_ARG);
+  for (int32_t d = 0; d < ndm; ++d)
+    if (!(dms[d] >= 0.0f) || !std::isfinite(dms[d])) return fail(SPS_ERR_INVALID_ARG);
+  const double ref = 1.0 / (f_ref_mhz * f_ref_mhz);
+  for (int32_t d = 0; d < ndm; ++d) {
+    const double dm = (double)dms[d];
+    for (int32_t f = 0; f < nchan; ++f) {
+      const double v = kDispersionConst * dm * (1.0 / (freqs_mhz[f] * freqs_mhz[f]) - ref) / tsamp_s;
+      const double r = std::floor(v + 0.5);
+      if (!(r <= (double)INT32_MAX)) return fail(SPS_ERR_INVALID_ARG);
+      delays[(size_t)d * nchan + f] = (int32_t)r;
+    }
+  }
+  return ok();
+}
+
+sps_dedisp* sps_dedisp_create(int32_t nchan, int64_t nsamp_in, int32_t ndm, const int32_t* delays) {
+  if (nchan < 1 || nchan > 65536 || ndm < 1 || nsamp_in < 1 || nsamp_in > (int64_t)INT32_MAX - 8192 || !delays) {
+    fail(SPS_ERR_INVALID_ARG);
+    return nullptr;
+  }
+  int32_t maxd = 0;
+  for (int64_t i = 0; i < (int64_t)ndm * nchan; ++i) {
+    if (delays[i] < 0) {
+      fail(SPS_ERR_INVALID_ARG);
+      return nullptr;
+    }
+    maxd = std::max(maxd, delays[i]);
+  }
+  if ((int64_t)maxd >= nsamp_in) {
+    fail(SPS_ERR_INVALID_ARG);
+    return nullptr;
+  }
+  // trials per workgroup: the most whose delays fit the LDS staging in every channel
+  const int64_t room = 4LL * (sps::kDedispSpanWords - 1) - 1030;
+  int32_t dd = 16;
+  std::vector<int32_t> dt;
+  int32_t ndm_pad = 0;
+  for (;; dd /= 2) {
+    ndm_pad = (ndm + dd - 1) / dd * dd;
+    dt.assign((size_t)nchan * ndm_pad, 0);
+    for (int32_t f = 0; f < nchan; ++f)
+      for (int32_t d = 0; d < ndm_pad; ++d)
+        dt[(size_t)f * ndm_pad + d] = delays[(size_t)std::min(d, ndm - 1) * nchan + f];
+    if (dd == 1 || delay_spread(dt, nchan, ndm_pad, dd) <= room) break;
+  }
+  sps_dedisp* k = new (std::nothrow) sps_dedisp;
+  if (!k) {
+    fail(SPS_ERR_OOM);
+    return nullptr;
+  }
+  k->nchan = nchan;
+  k->ndm = ndm;
+  k->ndm_pad = ndm_pad;
+  k->dd = dd;
+  k->nsamp_in = nsamp_in;
+  k->nsamp_out = nsamp_in - maxd;
+  k->d_delay = nullptr;
+  if (hipMalloc(&k->d_delay, dt.size() * sizeof(int32_t)) != hipSuccess) {
+    delete k;
+    fail(SPS_ERR_OOM);
+    return nullptr;
+  }
+  if (hipMemcpy(k->d_delay, dt.data(), dt.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(k->d_delay);
+    delete k;
+    fail(SPS_ERR_HIP);
+    return nullptr;
+  }
+  ok();
+  return k;
+}
+
+int64_t sps_dedisp_nsamp_out(const sps_dedisp* k) {
+  if (!k) {
+    fail(SPS_ERR_INVALID_ARG);
+    return -1;
+  }
+  return k->nsamp_out;
+}
+
+int sps_dedisp_run(sps_dedisp* k, const uint8_t* d_fil, hipStream_t stream, float* d_out) {
+  if (!k || !d_fil || !d_out || (reinterpret_cast<uintptr_t>(d_fil) & 3u)) return fail(SPS_ERR_INVALID_ARG);
+  sps::DedispArgs a;
+  a.fil32 = reinterpret_cast<const uint32_t*>(d_fil);
+  a.ld = k->nsamp_in;
+  a.total_bytes = (int64_t)k->nchan * k->nsamp_in;
+  a.nfull = a.total_bytes / 4;
+  a.nchan = k->nchan;
+  a.ndm = k->ndm;
+  a.ndm_pad = k->ndm_pad;
+  a.nsamp_out = (int32_t)k->nsamp_out;
+  a.dd = k->dd;
+  a.ngroups = k->ndm_pad / k->dd;
+  const int64_t ntime = (k->nsamp_out + 1023) / 1024;
+  const int64_t ntiles = ntime * a.ngroups;
+  if (ntiles > (int64_t)INT32_MAX - 8) return fail(SPS_ERR_INVALID_ARG);
+  a.ntiles = (int32_t)ntiles;
+  a.per_xcd = (int32_t)((ntiles + 7) / 8);
+  a.delay_t = k->d_delay;
+  a.out = d_out;
+  if (sps::launch_dedisp(a, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  return ok();
+}
+
+void sps_dedisp_destroy(sps_dedisp* k) {
+  if (!k) return;
+  (void)hipDeviceSynchronize();
+  if (k->d_delay) (void)hipFree(k->d_delay);
+  delete k;
+}
+
+}  // extern "C"

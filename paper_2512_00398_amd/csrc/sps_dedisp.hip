@@ -1,0 +1,124 @@
+// sps_dedisp.hip - incoherent dedispersion on the device (Heimdall++,
+// Section II-B, "Incoherent Dedispersion"; the DM of Eq. 1): for every trial
+// d, out[d][t] = sum over channels f of fil[f][t + delay[d][f]], from an 8-bit
+// channel-major filterbank to the FP32 [ndm][nsamp_out] block the search
+// consumes. Exact integer sums.
+//
+// Design (gfx950, wave64). A workgroup of 256 threads owns 1024 output
+// samples of DD consecutive trials (DD = 16 unless the trials' delays spread
+// too far for the LDS staging). For each channel it stages, with aligned
+// 4-byte loads, the bytes from t0 + min delay to t0 + 1024 + max delay of the
+// channel row into LDS; each thread then takes, for every trial, the 4 bytes
+// of its 4 consecutive output samples from there (two LDS words and one
+// v_alignbyte) and adds them as two pairs of 16-bit lanes (bytes 0 and 2,
+// bytes 1 and 3), flushing the pairs into 32-bit sums every 256 channels
+// (256 x 255 < 2^16). The arithmetic is one add per (trial, channel, output
+// sample); the data are re-read from L2 by each trial group, so workgroups
+// are ordered XCD by XCD over time tiles, all trial groups of a time tile on
+// one XCD, sharing its L2.
+#include <hip/hip_runtime.h>
+
+#include "sps_internal.h"
+
+namespace sps {
+namespace {
+
+constexpr int kDT = 1024;  // output samples per workgroup
+
+__device__ __forceinline__ uint32_t load_word(const DedispArgs& a, int64_t w) {
+  if (w < a.nfull) return a.fil32[w];
+  // the last, partial word of the filterbank: bytes past its end read as 0
+  const uint8_t* b = reinterpret_cast<const uint8_t*>(a.fil32);
+  uint32_t v = 0;
+  for (int q = 0; q < 4; ++q)
+    if (4 * w + q < a.total_bytes) v |= (uint32_t)b[4 * w + q] << (8 * q);
+  return v;
+}
+
+template <int DD>
+__global__ __launch_bounds__(256) void k_dedisp(DedispArgs a) {
+  __shared__ uint32_t buf[kDedispSpanWords];
+  // XCD-aware order: block b runs on XCD b % 8; give each XCD a contiguous
+  // range of tiles, trial groups fastest, so one time tile stays on one XCD
+  const int b = blockIdx.x;
+  const int tile = (b & 7) * a.per_xcd + (b >> 3);
+  if (tile >= a.ntiles) return;  // whole workgroup leaves; no barrier passed yet
+  const int dg = tile % a.ngroups, tt = tile / a.ngroups;
+  const int t0 = tt * kDT, d0 = dg * DD;
+  const int tid = threadIdx.x;
+
+  uint32_t lo[DD], hi[DD], acc[DD][4];
+#pragma unroll
+  for (int j = 0; j < DD; ++j) {
+    lo[j] = hi[j] = 0u;
+    acc[j][0] = acc[j][1] = acc[j][2] = acc[j][3] = 0u;
+  }
+  for (int f = 0; f < a.nchan; ++f) {
+    const int32_t* dl = a.delay_t + (int64_t)f * a.ndm_pad + d0;  // same for every thread
+    int dv[DD];
+    int dmin = INT_MAX, dmax = 0;
+#pragma unroll
+    for (int j = 0; j < DD; ++j) {
+      dv[j] = dl[j];
+      dmin = min(dmin, dv[j]);
+      dmax = max(dmax, dv[j]);
+    }
+    const int64_t src0 = (int64_t)f * a.ld + t0 + dmin;  // first byte needed
+    const int64_t w0 = src0 >> 2;
+    const int sh0 = (int)(src0 & 3);
+    const int nw = (sh0 + (dmax - dmin) + kDT + 3) / 4 + 1;  // <= kDedispSpanWords (host-checked)
+    __syncthreads();  // the previous channel's reads are done
+    for (int k = tid; k < nw; k += 256) buf[k] = load_word(a, w0 + k);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < DD; ++j) {
+      const int off = sh0 + (dv[j] - dmin) + 4 * tid;
+      const int w = off >> 2;
+      const uint32_t v = __builtin_amdgcn_alignbyte(buf[w + 1], buf[w], (uint32_t)(off & 3));
+      lo[j] += v & 0x00FF00FFu;         // samples 0 and 2
+      hi[j] += (v >> 8) & 0x00FF00FFu;  // samples 1 and 3
+    }
+    if ((f & 255) == 255 || f + 1 == a.nchan) {
+#pragma unroll
+      for (int j = 0; j < DD; ++j) {
+        acc[j][0] += lo[j] & 0xFFFFu;
+        acc[j][2] += lo[j] >> 16;
+        acc[j][1] += hi[j] & 0xFFFFu;
+        acc[j][3] += hi[j] >> 16;
+        lo[j] = hi[j] = 0u;
+      }
+    }
+  }
+  const int t = t0 + 4 * tid;
+#pragma unroll
+  for (int j = 0; j < DD; ++j) {
+    const int d = d0 + j;
+    if (d >= a.ndm) break;
+    float* o = a.out + (int64_t)d * a.nsamp_out;
+    if (t + 3 < a.nsamp_out && ((reinterpret_cast<uintptr_t>(o + t) & 15u) == 0)) {
+      *reinterpret_cast<float4*>(o + t) = make_float4((float)acc[j][0], (float)acc[j][1], (float)acc[j][2],
+                                                      (float)acc[j][3]);
+    } else {
+      for (int q = 0; q < 4; ++q)
+        if (t + q < a.nsamp_out) o[t + q] = (float)acc[j][q];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_dedisp(const DedispArgs& a, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  const dim3 g(8 * a.per_xcd), b(256);
+  switch (a.dd) {
+    case 16: hipLaunchKernelGGL(k_dedisp<16>, g, b, 0, s, a); break;
+    case 8: hipLaunchKernelGGL(k_dedisp<8>, g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_dedisp<4>, g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_dedisp<2>, g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_dedisp<1>, g, b, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sps

@@ -70,6 +70,23 @@ struct RowMadArgs {
   int32_t* mad;        // [rows][nblocks], overwritten
 };
 
+// Incoherent dedispersion: words of LDS staging per channel (16 KiB).
+constexpr int kDedispSpanWords = 4096;
+
+struct DedispArgs {
+  const uint32_t* fil32;  // filterbank bytes [nchan][ld], 4-byte aligned
+  int64_t ld;             // row stride in bytes (= nsamp_in)
+  int64_t nfull;          // whole 4-byte words in the filterbank
+  int64_t total_bytes;    // nchan * ld
+  int32_t nchan, ndm, ndm_pad, nsamp_out;
+  int32_t dd;             // trials per workgroup (16, 8, 4, 2 or 1)
+  int32_t ngroups;        // ndm_pad / dd
+  int32_t ntiles;         // ngroups * time tiles
+  int32_t per_xcd;        // tiles per XCD (grid = 8 * per_xcd)
+  const int32_t* delay_t; // [nchan][ndm_pad], trials past ndm repeat the last
+  float* out;             // [ndm][nsamp_out]
+};
+
 struct DetectArgs {
   const float* x;
   int64_t ld;
@@ -183,6 +200,7 @@ hipError_t launch_detect(const DetectArgs& a, hipStream_t s);
 hipError_t launch_fixup(const DetectArgs& a, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 hipError_t launch_row_mad(const RowMadArgs& a, hipStream_t s);
+hipError_t launch_dedisp(const DedispArgs& a, hipStream_t s);
 hipError_t launch_validate(const float* x, int64_t n, float bound, uint32_t* bad, hipStream_t s);
 hipError_t launch_stream_fold(const StreamArgs& a, hipStream_t s);
 hipError_t launch_stream_advance(const StreamArgs& a, hipStream_t s);

@@ -73,6 +73,11 @@ EXPORTS = [
     ("sps_cluster_run", ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
                                        _P]),
     ("sps_cluster_destroy", None, [_P]),
+    ("sps_dedisp_delays", ctypes.c_int, [ctypes.c_int32, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P, _P]),
+    ("sps_dedisp_create", _P, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P]),
+    ("sps_dedisp_nsamp_out", ctypes.c_int64, [_P]),
+    ("sps_dedisp_run", ctypes.c_int, [_P, _P, _P, _P]),
+    ("sps_dedisp_destroy", None, [_P]),
     ("sps_last_error", ctypes.c_int, []),
     ("sps_error_string", ctypes.c_char_p, [ctypes.c_int]),
 ]
@@ -419,6 +424,69 @@ class Clusterer:
     def close(self) -> None:
         if getattr(self, "_h", None):
             load().sps_cluster_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def dedisp_delays(freqs_mhz, f_ref_mhz: float, tsamp_s: float, dms) -> np.ndarray:
+    """Per-channel dispersion delays in samples, int32 [ndm][nchan] (sps_dedisp_delays)."""
+    f = np.ascontiguousarray(freqs_mhz, dtype=np.float64)
+    d = np.ascontiguousarray(dms, dtype=np.float32)
+    out = np.empty((d.size, f.size), dtype=np.int32)
+    rc = load().sps_dedisp_delays(f.size, f.ctypes.data, float(f_ref_mhz), float(tsamp_s), d.size, d.ctypes.data,
+                                  out.ctypes.data)
+    if rc:
+        raise SpsError(rc, "sps_dedisp_delays")
+    return out
+
+
+class Dedisperser:
+    """Incoherent dedispersion on the GPU (see include/sps.h): an 8-bit
+    channel-major filterbank [nchan][nsamp_in] to FP32 [ndm][nsamp_out]."""
+
+    def __init__(self, nchan: int, nsamp_in: int, delays):
+        lib = load()
+        tab = np.ascontiguousarray(delays, dtype=np.int32)
+        if tab.ndim != 2 or tab.shape[1] != nchan:
+            raise ValueError("delays must be int32 [ndm][nchan]")
+        self.nchan, self.nsamp_in, self.ndm = int(nchan), int(nsamp_in), int(tab.shape[0])
+        self._h = lib.sps_dedisp_create(self.nchan, self.nsamp_in, self.ndm, tab.ctypes.data)
+        if not self._h:
+            raise SpsError(lib.sps_last_error(), "sps_dedisp_create")
+        self.nsamp_out = int(lib.sps_dedisp_nsamp_out(self._h))
+
+    def alloc_out(self):
+        import torch
+        return torch.empty((self.ndm, self.nsamp_out), dtype=torch.float32, device="cuda")
+
+    def run(self, fil, out=None, stream=None):
+        """Dedisperse fil (uint8 GPU tensor [nchan][nsamp_in]) into out (FP32 [ndm][nsamp_out])."""
+        import torch
+        if fil.dtype != torch.uint8 or tuple(fil.shape) != (self.nchan, self.nsamp_in) or not fil.is_contiguous():
+            raise ValueError("filterbank must be a contiguous uint8 GPU tensor [nchan][nsamp_in]")
+        if out is None:
+            out = self.alloc_out()
+        if out.dtype != torch.float32 or tuple(out.shape) != (self.ndm, self.nsamp_out) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 GPU tensor [ndm][nsamp_out]")
+        rc = load().sps_dedisp_run(self._h, fil.data_ptr(), _stream_handle(stream), out.data_ptr())
+        if rc:
+            raise SpsError(rc, "sps_dedisp_run")
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().sps_dedisp_destroy(self._h)
             self._h = None
 
     def __del__(self):
