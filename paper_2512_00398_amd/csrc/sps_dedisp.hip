@@ -8,10 +8,12 @@
 // samples of DD consecutive trials (DD = 16 unless the trials' delays spread
 // too far for the LDS staging). For each channel it stages, with aligned
 // 4-byte loads, the bytes from t0 + min delay to t0 + 1024 + max delay of the
-// channel row into LDS; each thread then takes, for every trial, the 4 bytes
+// channel row into LDS (two buffers: the next channel's loads are in flight
+// while this channel is summed); each thread then takes, for every trial, the 4 bytes
 // of its 4 consecutive output samples from there (two LDS words and one
-// v_alignbyte) and adds them as two pairs of 16-bit lanes (bytes 0 and 2,
-// bytes 1 and 3), flushing the pairs into 32-bit sums every 256 channels
+// v_alignbyte, then two v_perm_b32 that place bytes 0 and 2, and bytes 1 and
+// 3, in the low bytes of two 16-bit lanes) and adds them as two pairs of
+// 16-bit sums, flushing the pairs into 32-bit sums every 256 channels
 // (256 x 255 < 2^16). The arithmetic is one add per (trial, channel, output
 // sample); the data are re-read from L2 by each trial group, so workgroups
 // are ordered XCD by XCD over time tiles, all trial groups of a time tile on
@@ -35,9 +37,39 @@ __device__ __forceinline__ uint32_t load_word(const DedispArgs& a, int64_t w) {
   return v;
 }
 
+// Delays of this workgroup's trials at channel f (the same for every thread)
+// and the LDS span they need: words from w0, first byte at sh0.
+template <int DD>
+struct ChanSpan {
+  int dv[DD];
+  int dmin, nw, sh0;
+  int64_t w0;
+};
+
+template <int DD>
+__device__ __forceinline__ ChanSpan<DD> chan_span(const DedispArgs& a, int f, int t0, int d0) {
+  ChanSpan<DD> c;
+  const int32_t* dl = a.delay_t + (int64_t)f * a.ndm_pad + d0;
+  c.dmin = INT_MAX;
+  int dmax = 0;
+#pragma unroll
+  for (int j = 0; j < DD; ++j) {
+    c.dv[j] = dl[j];
+    c.dmin = min(c.dmin, c.dv[j]);
+    dmax = max(dmax, c.dv[j]);
+  }
+  const int64_t src0 = (int64_t)f * a.ld + t0 + c.dmin;  // first byte needed
+  c.w0 = src0 >> 2;
+  c.sh0 = (int)(src0 & 3);
+  c.nw = (c.sh0 + (dmax - c.dmin) + kDT + 3) / 4 + 1;  // <= kDedispSpanWords (host-checked)
+  return c;
+}
+
 template <int DD>
 __global__ __launch_bounds__(256) void k_dedisp(DedispArgs a) {
-  __shared__ uint32_t buf[kDedispSpanWords];
+  // two staging buffers: channel f is read from one while channel f+1 is
+  // written to the other, one barrier per channel
+  __shared__ uint32_t buf[2][kDedispSpanWords];
   // XCD-aware order: block b runs on XCD b % 8; give each XCD a contiguous
   // range of tiles, trial groups fastest, so one time tile stays on one XCD
   const int b = blockIdx.x;
@@ -53,30 +85,30 @@ __global__ __launch_bounds__(256) void k_dedisp(DedispArgs a) {
     lo[j] = hi[j] = 0u;
     acc[j][0] = acc[j][1] = acc[j][2] = acc[j][3] = 0u;
   }
+  ChanSpan<DD> cur = chan_span<DD>(a, 0, t0, d0);
+  for (int k = tid; k < cur.nw; k += 256) buf[0][k] = load_word(a, cur.w0 + k);
+  __syncthreads();
   for (int f = 0; f < a.nchan; ++f) {
-    const int32_t* dl = a.delay_t + (int64_t)f * a.ndm_pad + d0;  // same for every thread
-    int dv[DD];
-    int dmin = INT_MAX, dmax = 0;
+    const int pb = f & 1;
+    // next channel's span: its first two words per thread are loaded now and
+    // stored after this channel's sums, so the loads overlap them
+    const bool more = f + 1 < a.nchan;
+    ChanSpan<DD> nxt = chan_span<DD>(a, more ? f + 1 : f, t0, d0);
+    const int nwn = more ? nxt.nw : 0;
+    const uint32_t q0 = tid < nwn ? load_word(a, nxt.w0 + tid) : 0u;
+    const uint32_t q1 = tid + 256 < nwn ? load_word(a, nxt.w0 + tid + 256) : 0u;
+    const uint32_t* B = buf[pb] + tid;
 #pragma unroll
     for (int j = 0; j < DD; ++j) {
-      dv[j] = dl[j];
-      dmin = min(dmin, dv[j]);
-      dmax = max(dmax, dv[j]);
-    }
-    const int64_t src0 = (int64_t)f * a.ld + t0 + dmin;  // first byte needed
-    const int64_t w0 = src0 >> 2;
-    const int sh0 = (int)(src0 & 3);
-    const int nw = (sh0 + (dmax - dmin) + kDT + 3) / 4 + 1;  // <= kDedispSpanWords (host-checked)
-    __syncthreads();  // the previous channel's reads are done
-    for (int k = tid; k < nw; k += 256) buf[k] = load_word(a, w0 + k);
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < DD; ++j) {
-      const int off = sh0 + (dv[j] - dmin) + 4 * tid;
-      const int w = off >> 2;
-      const uint32_t v = __builtin_amdgcn_alignbyte(buf[w + 1], buf[w], (uint32_t)(off & 3));
-      lo[j] += v & 0x00FF00FFu;         // samples 0 and 2
-      hi[j] += (v >> 8) & 0x00FF00FFu;  // samples 1 and 3
+      // this thread's 4 bytes start at byte 4*tid + base of the staged span;
+      // base mod 4 is the same in every lane (a scalar shift for v_alignbyte),
+      // and two constant byte selectors place samples 0 and 2, then 1 and 3,
+      // in the low bytes of two 16-bit lanes (selector byte 0x0c gives zero)
+      const int base = cur.sh0 + (cur.dv[j] - cur.dmin);
+      const uint32_t x0 = B[base >> 2], x1 = B[(base >> 2) + 1];
+      const uint32_t v = __builtin_amdgcn_alignbyte(x1, x0, (uint32_t)(base & 3));
+      lo[j] += __builtin_amdgcn_perm(0u, v, 0x0c020c00u);  // samples 0 and 2
+      hi[j] += __builtin_amdgcn_perm(0u, v, 0x0c030c01u);  // samples 1 and 3
     }
     if ((f & 255) == 255 || f + 1 == a.nchan) {
 #pragma unroll
@@ -88,6 +120,12 @@ __global__ __launch_bounds__(256) void k_dedisp(DedispArgs a) {
         lo[j] = hi[j] = 0u;
       }
     }
+    uint32_t* N = buf[pb ^ 1];
+    if (tid < nwn) N[tid] = q0;
+    if (tid + 256 < nwn) N[tid + 256] = q1;
+    for (int k = tid + 512; k < nwn; k += 256) N[k] = load_word(a, nxt.w0 + k);  // wide spreads only
+    cur = nxt;
+    __syncthreads();
   }
   const int t = t0 + 4 * tid;
 #pragma unroll
