@@ -37,6 +37,7 @@ KERNEL_SOURCES = {
                _CSRC + "sps_api.hip", "include/sps.h"],
     "block_stats": [_CSRC + "sps_stats.hip", _CSRC + "sps_wave.h", _CSRC + "sps_internal.h", _CSRC + "sps_api.hip",
                     "include/sps.h"],
+    "dedisp": [_CSRC + "sps_dedisp.hip", _CSRC + "sps_internal.h", _CSRC + "sps_api.hip", "include/sps.h"],
 }
 MEASURED_TRAFFIC = {
     # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md
@@ -249,7 +250,7 @@ def bench_dedisp(args):
         "config": {"workload": "dedisp: 1024 channels 1050-1450 MHz, tsamp 49.152 us, 1024 trial DMs 0-1000, "
                                "%d output samples (%d input)" % (nout, nin)},
         "roofline": {"bound": "alu", "kernel": "dedisp", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic("dedisp"),
                      "algorithmic_ops": adds, "algorithmic_bytes": float(nchan) * nin + 4.0 * ndm * nout},
         "kernel_ms": kms, "pipeline_ms_per_chunk": pipe_ms, "pipeline_candidates": n, "cpu_baseline": cpu}))
 
