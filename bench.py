@@ -40,9 +40,11 @@ KERNEL_SOURCES = {
     "dedisp": [_CSRC + "sps_dedisp.hip", _CSRC + "sps_internal.h", _CSRC + "sps_api.hip", "include/sps.h"],
 }
 MEASURED_TRAFFIC = {
-    # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md
-    "detect": ("e5b2798e703d9c6e", (2237778 * 2 + 170181) * 1024),
-    "block_stats": ("3060eeb6e072252e", (4349622 * 2 + 138194) * 1024),
+    # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md,
+    # profiles/dedisp_1024ch_1024dm_2p18.md
+    "detect": ("170687bb4c35ed3d", (2237780 * 2 + 170218) * 1024),
+    "block_stats": ("939a0a87be199440", (4349789 * 2 + 137112) * 1024),
+    "dedisp": ("657cf466141e8247", (3273743 * 2 + 1048576) * 1024),
 }
 
 
