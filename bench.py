@@ -42,9 +42,9 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md,
     # profiles/dedisp_1024ch_1024dm_2p18.md
-    "detect": ("170687bb4c35ed3d", (2237780 * 2 + 170218) * 1024),
-    "block_stats": ("939a0a87be199440", (4349789 * 2 + 137112) * 1024),
-    "dedisp": ("657cf466141e8247", (3273743 * 2 + 1048576) * 1024),
+    "detect": ("c940ae19200ba86e", (2237780 * 2 + 170191) * 1024),
+    "block_stats": ("4b8e310b9e7d50cb", (4349813 * 2 + 137084) * 1024),
+    "dedisp": ("383490aa81e99e8c", (3394912 * 2 + 1048576) * 1024),
 }
 
 

@@ -1428,9 +1428,11 @@ void sps_cluster_destroy(sps_clusterer* k) {
 // ---------------------------------------------------------------- dedispersion
 
 struct sps_dedisp {
-  int32_t nchan, ndm, ndm_pad, dd;
+  int32_t nchan, ndm, ndm_pad, dd, ngroups;
   int64_t nsamp_in, nsamp_out;
-  int32_t* d_delay;  // [nchan][ndm_pad]
+  void* d_mem;               // one allocation: span table, then offsets
+  sps::DedispSpan* d_span;   // [nchan][ngroups]
+  int32_t* d_base;           // [nchan][ndm_pad]
 };
 
 namespace {
@@ -1509,6 +1511,28 @@ sps_dedisp* sps_dedisp_create(int32_t nchan, int64_t nsamp_in, int32_t ndm, cons
         dt[(size_t)f * ndm_pad + d] = delays[(size_t)std::min(d, ndm - 1) * nchan + f];
     if (dd == 1 || delay_spread(dt, nchan, ndm_pad, dd) <= room) break;
   }
+  // Per (channel, trial group): the staged span at time tile 0 (a tile
+  // starts a multiple of 4 bytes later, so only the first word moves) and
+  // each trial's byte offset into it.
+  const int32_t ngroups = ndm_pad / dd;
+  std::vector<sps::DedispSpan> span((size_t)nchan * ngroups);
+  std::vector<int32_t> base((size_t)nchan * ndm_pad);
+  for (int32_t f = 0; f < nchan; ++f)
+    for (int32_t g = 0; g < ngroups; ++g) {
+      const int32_t* p = &dt[(size_t)f * ndm_pad + (size_t)g * dd];
+      int32_t lo = p[0], hi = p[0];
+      for (int32_t j = 1; j < dd; ++j) {
+        lo = std::min(lo, p[j]);
+        hi = std::max(hi, p[j]);
+      }
+      const int64_t src0 = (int64_t)f * nsamp_in + lo;  // first byte needed at tile 0
+      const int32_t sh0 = (int32_t)(src0 & 3);
+      sps::DedispSpan& sg = span[(size_t)f * ngroups + g];
+      sg.w0 = src0 >> 2;
+      sg.nw = (sh0 + (hi - lo) + 1024 + 3) / 4 + 1;  // <= kDedispSpanWords by the choice of dd
+      sg.pad = 0;
+      for (int32_t j = 0; j < dd; ++j) base[(size_t)f * ndm_pad + (size_t)g * dd + j] = sh0 + (p[j] - lo);
+    }
   sps_dedisp* k = new (std::nothrow) sps_dedisp;
   if (!k) {
     fail(SPS_ERR_OOM);
@@ -1518,16 +1542,21 @@ sps_dedisp* sps_dedisp_create(int32_t nchan, int64_t nsamp_in, int32_t ndm, cons
   k->ndm = ndm;
   k->ndm_pad = ndm_pad;
   k->dd = dd;
+  k->ngroups = ngroups;
   k->nsamp_in = nsamp_in;
   k->nsamp_out = nsamp_in - maxd;
-  k->d_delay = nullptr;
-  if (hipMalloc(&k->d_delay, dt.size() * sizeof(int32_t)) != hipSuccess) {
+  k->d_mem = nullptr;
+  const size_t span_bytes = span.size() * sizeof(sps::DedispSpan), base_bytes = base.size() * sizeof(int32_t);
+  if (hipMalloc(&k->d_mem, span_bytes + base_bytes) != hipSuccess) {
     delete k;
     fail(SPS_ERR_OOM);
     return nullptr;
   }
-  if (hipMemcpy(k->d_delay, dt.data(), dt.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(k->d_delay);
+  k->d_span = static_cast<sps::DedispSpan*>(k->d_mem);
+  k->d_base = reinterpret_cast<int32_t*>(static_cast<char*>(k->d_mem) + span_bytes);
+  if (hipMemcpy(k->d_span, span.data(), span_bytes, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(k->d_base, base.data(), base_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(k->d_mem);
     delete k;
     fail(SPS_ERR_HIP);
     return nullptr;
@@ -1556,13 +1585,14 @@ int sps_dedisp_run(sps_dedisp* k, const uint8_t* d_fil, hipStream_t stream, floa
   a.ndm_pad = k->ndm_pad;
   a.nsamp_out = (int32_t)k->nsamp_out;
   a.dd = k->dd;
-  a.ngroups = k->ndm_pad / k->dd;
+  a.ngroups = k->ngroups;
   const int64_t ntime = (k->nsamp_out + 1023) / 1024;
   const int64_t ntiles = ntime * a.ngroups;
   if (ntiles > (int64_t)INT32_MAX - 8) return fail(SPS_ERR_INVALID_ARG);
   a.ntiles = (int32_t)ntiles;
   a.per_xcd = (int32_t)((ntiles + 7) / 8);
-  a.delay_t = k->d_delay;
+  a.span = k->d_span;
+  a.base = k->d_base;
   a.out = d_out;
   if (sps::launch_dedisp(a, stream) != hipSuccess) return fail(SPS_ERR_HIP);
   return ok();
@@ -1571,7 +1601,7 @@ int sps_dedisp_run(sps_dedisp* k, const uint8_t* d_fil, hipStream_t stream, floa
 void sps_dedisp_destroy(sps_dedisp* k) {
   if (!k) return;
   (void)hipDeviceSynchronize();
-  if (k->d_delay) (void)hipFree(k->d_delay);
+  if (k->d_mem) (void)hipFree(k->d_mem);
   delete k;
 }
 

@@ -37,34 +37,6 @@ __device__ __forceinline__ uint32_t load_word(const DedispArgs& a, int64_t w) {
   return v;
 }
 
-// Delays of this workgroup's trials at channel f (the same for every thread)
-// and the LDS span they need: words from w0, first byte at sh0.
-template <int DD>
-struct ChanSpan {
-  int dv[DD];
-  int dmin, nw, sh0;
-  int64_t w0;
-};
-
-template <int DD>
-__device__ __forceinline__ ChanSpan<DD> chan_span(const DedispArgs& a, int f, int t0, int d0) {
-  ChanSpan<DD> c;
-  const int32_t* dl = a.delay_t + (int64_t)f * a.ndm_pad + d0;
-  c.dmin = INT_MAX;
-  int dmax = 0;
-#pragma unroll
-  for (int j = 0; j < DD; ++j) {
-    c.dv[j] = dl[j];
-    c.dmin = min(c.dmin, c.dv[j]);
-    dmax = max(dmax, c.dv[j]);
-  }
-  const int64_t src0 = (int64_t)f * a.ld + t0 + c.dmin;  // first byte needed
-  c.w0 = src0 >> 2;
-  c.sh0 = (int)(src0 & 3);
-  c.nw = (c.sh0 + (dmax - c.dmin) + kDT + 3) / 4 + 1;  // <= kDedispSpanWords (host-checked)
-  return c;
-}
-
 template <int DD>
 __global__ __launch_bounds__(256) void k_dedisp(DedispArgs a) {
   // two staging buffers: channel f is read from one while channel f+1 is
@@ -78,6 +50,12 @@ __global__ __launch_bounds__(256) void k_dedisp(DedispArgs a) {
   const int dg = tile % a.ngroups, tt = tile / a.ngroups;
   const int t0 = tt * kDT, d0 = dg * DD;
   const int tid = threadIdx.x;
+  // spans and offsets were laid out on the host (t0 is a multiple of 4, so a
+  // tile only moves the span by whole words): the channel loop reads them
+  // with scalar loads and does no delay arithmetic
+  const DedispSpan* sp = a.span + dg;
+  const int32_t* bs = a.base + d0;
+  const int64_t tw = t0 >> 2;
 
   uint32_t lo[DD], hi[DD], acc[DD][4];
 #pragma unroll
@@ -85,28 +63,32 @@ __global__ __launch_bounds__(256) void k_dedisp(DedispArgs a) {
     lo[j] = hi[j] = 0u;
     acc[j][0] = acc[j][1] = acc[j][2] = acc[j][3] = 0u;
   }
-  ChanSpan<DD> cur = chan_span<DD>(a, 0, t0, d0);
-  for (int k = tid; k < cur.nw; k += 256) buf[0][k] = load_word(a, cur.w0 + k);
+  {
+    const DedispSpan s0 = sp[0];
+    for (int k = tid; k < s0.nw; k += 256) buf[0][k] = load_word(a, s0.w0 + tw + k);
+  }
   __syncthreads();
   for (int f = 0; f < a.nchan; ++f) {
     const int pb = f & 1;
     // next channel's span: its first two words per thread are loaded now and
     // stored after this channel's sums, so the loads overlap them
     const bool more = f + 1 < a.nchan;
-    ChanSpan<DD> nxt = chan_span<DD>(a, more ? f + 1 : f, t0, d0);
-    const int nwn = more ? nxt.nw : 0;
-    const uint32_t q0 = tid < nwn ? load_word(a, nxt.w0 + tid) : 0u;
-    const uint32_t q1 = tid + 256 < nwn ? load_word(a, nxt.w0 + tid + 256) : 0u;
+    const DedispSpan sn = sp[(int64_t)(more ? f + 1 : f) * a.ngroups];
+    const int nwn = more ? sn.nw : 0;
+    const int64_t wn = sn.w0 + tw;
+    const uint32_t q0 = tid < nwn ? load_word(a, wn + tid) : 0u;
+    const uint32_t q1 = tid + 256 < nwn ? load_word(a, wn + tid + 256) : 0u;
     const uint32_t* B = buf[pb] + tid;
+    const int32_t* bf = bs + (int64_t)f * a.ndm_pad;
 #pragma unroll
     for (int j = 0; j < DD; ++j) {
       // this thread's 4 bytes start at byte 4*tid + base of the staged span;
-      // base mod 4 is the same in every lane (a scalar shift for v_alignbyte),
-      // and two constant byte selectors place samples 0 and 2, then 1 and 3,
-      // in the low bytes of two 16-bit lanes (selector byte 0x0c gives zero)
-      const int base = cur.sh0 + (cur.dv[j] - cur.dmin);
+      // v_alignbyte takes the shift from the low 2 bits of base (the same in
+      // every lane), and two constant byte selectors place samples 0 and 2,
+      // then 1 and 3, in the low bytes of two 16-bit lanes (0x0c gives zero)
+      const int base = bf[j];
       const uint32_t x0 = B[base >> 2], x1 = B[(base >> 2) + 1];
-      const uint32_t v = __builtin_amdgcn_alignbyte(x1, x0, (uint32_t)(base & 3));
+      const uint32_t v = __builtin_amdgcn_alignbyte(x1, x0, (uint32_t)base);
       lo[j] += __builtin_amdgcn_perm(0u, v, 0x0c020c00u);  // samples 0 and 2
       hi[j] += __builtin_amdgcn_perm(0u, v, 0x0c030c01u);  // samples 1 and 3
     }
@@ -123,8 +105,7 @@ __global__ __launch_bounds__(256) void k_dedisp(DedispArgs a) {
     uint32_t* N = buf[pb ^ 1];
     if (tid < nwn) N[tid] = q0;
     if (tid + 256 < nwn) N[tid + 256] = q1;
-    for (int k = tid + 512; k < nwn; k += 256) N[k] = load_word(a, nxt.w0 + k);  // wide spreads only
-    cur = nxt;
+    for (int k = tid + 512; k < nwn; k += 256) N[k] = load_word(a, wn + k);  // wide spreads only
     __syncthreads();
   }
   const int t = t0 + 4 * tid;

@@ -73,6 +73,14 @@ struct RowMadArgs {
 // Incoherent dedispersion: words of LDS staging per channel (16 KiB).
 constexpr int kDedispSpanWords = 4096;
 
+// Staged span of one channel for one trial group, at time tile 0 (tile t
+// starts 256 t words later): first 4-byte word and word count.
+struct DedispSpan {
+  int64_t w0;
+  int32_t nw;
+  int32_t pad;
+};
+
 struct DedispArgs {
   const uint32_t* fil32;  // filterbank bytes [nchan][ld], 4-byte aligned
   int64_t ld;             // row stride in bytes (= nsamp_in)
@@ -83,7 +91,10 @@ struct DedispArgs {
   int32_t ngroups;        // ndm_pad / dd
   int32_t ntiles;         // ngroups * time tiles
   int32_t per_xcd;        // tiles per XCD (grid = 8 * per_xcd)
-  const int32_t* delay_t; // [nchan][ndm_pad], trials past ndm repeat the last
+  const DedispSpan* span; // [nchan][ngroups]
+  // per channel f and trial d: byte offset of the trial's first sample in its
+  // group's staged span (trials past ndm repeat the last)
+  const int32_t* base;    // [nchan][ndm_pad]
   float* out;             // [ndm][nsamp_out]
 };
 
