@@ -42,9 +42,9 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md,
     # profiles/dedisp_1024ch_1024dm_2p18.md
-    "detect": ("c940ae19200ba86e", (2237780 * 2 + 170191) * 1024),
-    "block_stats": ("4b8e310b9e7d50cb", (4349813 * 2 + 137084) * 1024),
-    "dedisp": ("383490aa81e99e8c", (3394912 * 2 + 1048576) * 1024),
+    "detect": ("78d81e7afa14d986", (2237780 * 2 + 170200) * 1024),
+    "block_stats": ("ea3e23d3779546d3", (4349797 * 2 + 137138) * 1024),
+    "dedisp": ("e4ae1515ef782f64", (3448164 * 2 + 1048576) * 1024),
 }
 
 

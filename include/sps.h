@@ -296,7 +296,7 @@ int sps_footprint(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baselin
  *   stream-ordered; tolerances must be >= 0, samples within int32, dm_idx
  *   < 2^27 and widths powers of two up to 2^31. A context serves one stream
  *   at a time.
- * sps_cluster_destroy: waits for the device and frees the context (NULL-safe).
+ * sps_cluster_destroy: waits for the context's last run and frees it (NULL-safe).
  */
 typedef struct {
   int32_t sample;     /* best member: boxcar start */
@@ -346,7 +346,7 @@ void sps_cluster_destroy(sps_clusterer* k);
  *   exact integers (below 2^24 for nchan <= 65793, the domain sps_search
  *   accepts). Asynchronous on `stream`; SPS_ERR_INVALID_ARG (NULL or
  *   misaligned pointers), SPS_ERR_HIP (launch failure).
- * sps_dedisp_destroy: waits for the device and frees the object (NULL-safe).
+ * sps_dedisp_destroy: waits for the object's last run and frees it (NULL-safe).
  */
 typedef struct sps_dedisp sps_dedisp;
 

@@ -1354,6 +1354,8 @@ struct sps_clusterer {
   uint32_t cap;
   void* mem;
   sps::ClusterScratch s;
+  hipEvent_t done;  // end of the last run's work (destroy waits for it)
+  bool pending;
 };
 
 extern "C" {
@@ -1383,8 +1385,15 @@ sps_clusterer* sps_cluster_create(uint32_t max_cands) {
   }
   k->cap = max_cands;
   k->mem = nullptr;
+  k->pending = false;
+  if (hipEventCreateWithFlags(&k->done, hipEventDisableTiming) != hipSuccess) {
+    delete k;
+    fail(SPS_ERR_HIP);
+    return nullptr;
+  }
   if (hipMalloc(&k->mem, off) != hipSuccess) {
     (void)hipGetLastError();
+    (void)hipEventDestroy(k->done);
     delete k;
     fail(SPS_ERR_OOM);
     return nullptr;
@@ -1413,12 +1422,15 @@ int sps_cluster_run(sps_clusterer* k, const sps_cand* d_cands, uint32_t n, int32
     return fail(SPS_ERR_INVALID_ARG);
   if (sps::launch_cluster(d_cands, n, time_tol, dm_tol, width_tol, k->s, d_out, d_nout, stream) != hipSuccess)
     return fail(SPS_ERR_HIP);
+  if (hipEventRecord(k->done, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  k->pending = true;
   return ok();
 }
 
 void sps_cluster_destroy(sps_clusterer* k) {
   if (!k) return;
-  (void)hipDeviceSynchronize();
+  if (k->pending) (void)hipEventSynchronize(k->done);
+  (void)hipEventDestroy(k->done);
   if (k->mem) (void)hipFree(k->mem);
   delete k;
 }
@@ -1433,6 +1445,8 @@ struct sps_dedisp {
   void* d_mem;               // one allocation: span table, then offsets
   sps::DedispSpan* d_span;   // [nchan][ngroups]
   int32_t* d_base;           // [nchan][ndm_pad]
+  hipEvent_t done;           // end of the last run's work (destroy waits for it)
+  bool pending;
 };
 
 namespace {
@@ -1546,8 +1560,16 @@ sps_dedisp* sps_dedisp_create(int32_t nchan, int64_t nsamp_in, int32_t ndm, cons
   k->nsamp_in = nsamp_in;
   k->nsamp_out = nsamp_in - maxd;
   k->d_mem = nullptr;
+  k->pending = false;
+  if (hipEventCreateWithFlags(&k->done, hipEventDisableTiming) != hipSuccess) {
+    delete k;
+    fail(SPS_ERR_HIP);
+    return nullptr;
+  }
   const size_t span_bytes = span.size() * sizeof(sps::DedispSpan), base_bytes = base.size() * sizeof(int32_t);
   if (hipMalloc(&k->d_mem, span_bytes + base_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipEventDestroy(k->done);
     delete k;
     fail(SPS_ERR_OOM);
     return nullptr;
@@ -1557,6 +1579,7 @@ sps_dedisp* sps_dedisp_create(int32_t nchan, int64_t nsamp_in, int32_t ndm, cons
   if (hipMemcpy(k->d_span, span.data(), span_bytes, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(k->d_base, base.data(), base_bytes, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(k->d_mem);
+    (void)hipEventDestroy(k->done);
     delete k;
     fail(SPS_ERR_HIP);
     return nullptr;
@@ -1595,12 +1618,15 @@ int sps_dedisp_run(sps_dedisp* k, const uint8_t* d_fil, hipStream_t stream, floa
   a.base = k->d_base;
   a.out = d_out;
   if (sps::launch_dedisp(a, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  if (hipEventRecord(k->done, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  k->pending = true;
   return ok();
 }
 
 void sps_dedisp_destroy(sps_dedisp* k) {
   if (!k) return;
-  (void)hipDeviceSynchronize();
+  if (k->pending) (void)hipEventSynchronize(k->done);
+  (void)hipEventDestroy(k->done);
   if (k->d_mem) (void)hipFree(k->d_mem);
   delete k;
 }

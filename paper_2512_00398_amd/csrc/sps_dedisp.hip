@@ -8,8 +8,9 @@
 // samples of DD consecutive trials (DD = 16 unless the trials' delays spread
 // too far for the LDS staging). For each channel it stages, with aligned
 // 4-byte loads, the bytes from t0 + min delay to t0 + 1024 + max delay of the
-// channel row into LDS (two buffers: the next channel's loads are in flight
-// while this channel is summed); each thread then takes, for every trial, the 4 bytes
+// channel row into LDS, two channels per stage (two stages: the next pair's
+// loads are in flight while this pair is summed, one barrier per pair); each
+// thread then takes, for every trial, the 4 bytes
 // of its 4 consecutive output samples from there (two LDS words and one
 // v_alignbyte, then two v_perm_b32 that place bytes 0 and 2, and bytes 1 and
 // 3, in the low bytes of two 16-bit lanes) and adds them as two pairs of
@@ -37,11 +38,31 @@ __device__ __forceinline__ uint32_t load_word(const DedispArgs& a, int64_t w) {
   return v;
 }
 
+// Sums of one staged channel into the 16-bit pairs (B: this thread's view of
+// the span; bf: the trials' byte offsets into it).
+template <int DD>
+__device__ __forceinline__ void add_channel(const uint32_t* B, const int32_t* bf, uint32_t (&lo)[DD],
+                                            uint32_t (&hi)[DD]) {
+#pragma unroll
+  for (int j = 0; j < DD; ++j) {
+    // this thread's 4 bytes start at byte 4*tid + base of the staged span;
+    // v_alignbyte takes the shift from the low 2 bits of base (the same in
+    // every lane), and two constant byte selectors place samples 0 and 2,
+    // then 1 and 3, in the low bytes of two 16-bit lanes (0x0c gives zero)
+    const int base = bf[j];
+    const uint32_t x0 = B[base >> 2], x1 = B[(base >> 2) + 1];
+    const uint32_t v = __builtin_amdgcn_alignbyte(x1, x0, (uint32_t)base);
+    lo[j] += __builtin_amdgcn_perm(0u, v, 0x0c020c00u);  // samples 0 and 2
+    hi[j] += __builtin_amdgcn_perm(0u, v, 0x0c030c01u);  // samples 1 and 3
+  }
+}
+
 template <int DD>
 __global__ __launch_bounds__(256) void k_dedisp(DedispArgs a) {
-  // two staging buffers: channel f is read from one while channel f+1 is
-  // written to the other, one barrier per channel
-  __shared__ uint32_t buf[2][kDedispSpanWords];
+  // Channels go in pairs: one stage holds two channel spans; stage s is
+  // summed from one buffer while stage s+1 is written to the other, one
+  // barrier per two channels.
+  __shared__ uint32_t buf[2][2][kDedispSpanWords];
   // XCD-aware order: block b runs on XCD b % 8; give each XCD a contiguous
   // range of tiles, trial groups fastest, so one time tile stays on one XCD
   const int b = blockIdx.x;
@@ -56,6 +77,7 @@ __global__ __launch_bounds__(256) void k_dedisp(DedispArgs a) {
   const DedispSpan* sp = a.span + dg;
   const int32_t* bs = a.base + d0;
   const int64_t tw = t0 >> 2;
+  const int nchan = a.nchan;
 
   uint32_t lo[DD], hi[DD], acc[DD][4];
 #pragma unroll
@@ -63,36 +85,30 @@ __global__ __launch_bounds__(256) void k_dedisp(DedispArgs a) {
     lo[j] = hi[j] = 0u;
     acc[j][0] = acc[j][1] = acc[j][2] = acc[j][3] = 0u;
   }
-  {
-    const DedispSpan s0 = sp[0];
-    for (int k = tid; k < s0.nw; k += 256) buf[0][k] = load_word(a, s0.w0 + tw + k);
+  // stage 0: channels 0 and 1 (if any)
+  for (int c = 0; c < 2 && c < nchan; ++c) {
+    const DedispSpan s0 = sp[(int64_t)c * a.ngroups];
+    for (int k = tid; k < s0.nw; k += 256) buf[0][c][k] = load_word(a, s0.w0 + tw + k);
   }
   __syncthreads();
-  for (int f = 0; f < a.nchan; ++f) {
-    const int pb = f & 1;
-    // next channel's span: its first two words per thread are loaded now and
-    // stored after this channel's sums, so the loads overlap them
-    const bool more = f + 1 < a.nchan;
-    const DedispSpan sn = sp[(int64_t)(more ? f + 1 : f) * a.ngroups];
-    const int nwn = more ? sn.nw : 0;
-    const int64_t wn = sn.w0 + tw;
-    const uint32_t q0 = tid < nwn ? load_word(a, wn + tid) : 0u;
-    const uint32_t q1 = tid + 256 < nwn ? load_word(a, wn + tid + 256) : 0u;
-    const uint32_t* B = buf[pb] + tid;
-    const int32_t* bf = bs + (int64_t)f * a.ndm_pad;
-#pragma unroll
-    for (int j = 0; j < DD; ++j) {
-      // this thread's 4 bytes start at byte 4*tid + base of the staged span;
-      // v_alignbyte takes the shift from the low 2 bits of base (the same in
-      // every lane), and two constant byte selectors place samples 0 and 2,
-      // then 1 and 3, in the low bytes of two 16-bit lanes (0x0c gives zero)
-      const int base = bf[j];
-      const uint32_t x0 = B[base >> 2], x1 = B[(base >> 2) + 1];
-      const uint32_t v = __builtin_amdgcn_alignbyte(x1, x0, (uint32_t)base);
-      lo[j] += __builtin_amdgcn_perm(0u, v, 0x0c020c00u);  // samples 0 and 2
-      hi[j] += __builtin_amdgcn_perm(0u, v, 0x0c030c01u);  // samples 1 and 3
-    }
-    if ((f & 255) == 255 || f + 1 == a.nchan) {
+  for (int f = 0; f < nchan; f += 2) {
+    const int pb = (f >> 1) & 1;
+    const bool two = f + 1 < nchan;
+    // next stage's spans: the first two words per thread of each are loaded
+    // now and stored after this stage's sums, so the loads overlap them
+    const bool m0 = f + 2 < nchan, m1 = f + 3 < nchan;
+    const DedispSpan n0 = sp[(int64_t)(m0 ? f + 2 : f) * a.ngroups];
+    const DedispSpan n1 = sp[(int64_t)(m1 ? f + 3 : f) * a.ngroups];
+    const int nw0 = m0 ? n0.nw : 0, nw1 = m1 ? n1.nw : 0;
+    const int64_t w0 = n0.w0 + tw, w1 = n1.w0 + tw;
+    const uint32_t q00 = tid < nw0 ? load_word(a, w0 + tid) : 0u;
+    const uint32_t q01 = tid + 256 < nw0 ? load_word(a, w0 + tid + 256) : 0u;
+    const uint32_t q10 = tid < nw1 ? load_word(a, w1 + tid) : 0u;
+    const uint32_t q11 = tid + 256 < nw1 ? load_word(a, w1 + tid + 256) : 0u;
+    add_channel<DD>(buf[pb][0] + tid, bs + (int64_t)f * a.ndm_pad, lo, hi);
+    if (two) add_channel<DD>(buf[pb][1] + tid, bs + (int64_t)(f + 1) * a.ndm_pad, lo, hi);
+    // 256 is even: a flush point (every 256 channels) always ends a pair
+    if (((f + 1) & 255) == 255 || f + 2 >= nchan) {
 #pragma unroll
       for (int j = 0; j < DD; ++j) {
         acc[j][0] += lo[j] & 0xFFFFu;
@@ -102,10 +118,14 @@ __global__ __launch_bounds__(256) void k_dedisp(DedispArgs a) {
         lo[j] = hi[j] = 0u;
       }
     }
-    uint32_t* N = buf[pb ^ 1];
-    if (tid < nwn) N[tid] = q0;
-    if (tid + 256 < nwn) N[tid + 256] = q1;
-    for (int k = tid + 512; k < nwn; k += 256) N[k] = load_word(a, wn + k);  // wide spreads only
+    uint32_t* N0 = buf[pb ^ 1][0];
+    uint32_t* N1 = buf[pb ^ 1][1];
+    if (tid < nw0) N0[tid] = q00;
+    if (tid + 256 < nw0) N0[tid + 256] = q01;
+    if (tid < nw1) N1[tid] = q10;
+    if (tid + 256 < nw1) N1[tid + 256] = q11;
+    for (int k = tid + 512; k < nw0; k += 256) N0[k] = load_word(a, w0 + k);  // wide spreads only
+    for (int k = tid + 512; k < nw1; k += 256) N1[k] = load_word(a, w1 + k);
     __syncthreads();
   }
   const int t = t0 + 4 * tid;

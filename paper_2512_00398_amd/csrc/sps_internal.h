@@ -70,8 +70,9 @@ struct RowMadArgs {
   int32_t* mad;        // [rows][nblocks], overwritten
 };
 
-// Incoherent dedispersion: words of LDS staging per channel (16 KiB).
-constexpr int kDedispSpanWords = 4096;
+// Incoherent dedispersion: words of LDS staging per channel span (8 KiB;
+// four spans per workgroup).
+constexpr int kDedispSpanWords = 2048;
 
 // Staged span of one channel for one trial group, at time tile 0 (tile t
 // starts 256 t words later): first 4-byte word and word count.
