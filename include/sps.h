@@ -350,6 +350,20 @@ void sps_cluster_destroy(sps_clusterer* k);
  */
 typedef struct sps_dedisp sps_dedisp;
 
+/* ---- Broadband (zero-DM) RFI excision (Heimdall++ Section II-B, "RFI
+ * Mitigation", the stage before dedispersion in Algorithm 1).
+ * sps_zero_dm: d_in and d_out are device uint8 filterbanks, channel-major
+ *   [nchan][nsamp] (row stride nsamp bytes); d_out may equal d_in (in place)
+ *   but must not otherwise overlap it. For every time sample t,
+ *     z_t = floor((2 * sum_f in[f][t] + nchan) / (2 * nchan))
+ *   (the channel mean rounded half up) and
+ *     out[f][t] = min(255, max(0, in[f][t] - z_t + offset)).
+ *   nchan in [1, 65536], nsamp in [1, INT32_MAX - 8192], offset in [0, 255]. Asynchronous on
+ *   `stream`; SPS_ERR_INVALID_ARG (bad sizes, NULL or overlapping buffers),
+ *   SPS_ERR_HIP (launch failure). */
+int sps_zero_dm(const uint8_t* d_in, int32_t nchan, int64_t nsamp, int32_t offset, hipStream_t stream,
+                uint8_t* d_out);
+
 int sps_dedisp_delays(int32_t nchan, const double* freqs_mhz, double f_ref_mhz, double tsamp_s, int32_t ndm,
                       const float* dms, int32_t* delays);
 sps_dedisp* sps_dedisp_create(int32_t nchan, int64_t nsamp_in, int32_t ndm, const int32_t* delays);

@@ -1623,6 +1623,26 @@ int sps_dedisp_run(sps_dedisp* k, const uint8_t* d_fil, hipStream_t stream, floa
   return ok();
 }
 
+int sps_zero_dm(const uint8_t* d_in, int32_t nchan, int64_t nsamp, int32_t offset, hipStream_t stream,
+                uint8_t* d_out) {
+  if (!d_in || !d_out || nchan < 1 || nchan > 65536 || nsamp < 1 || nsamp > (int64_t)INT32_MAX - 8192 || offset < 0 ||
+      offset > 255)
+    return fail(SPS_ERR_INVALID_ARG);
+  // the output either is the input or does not overlap it
+  const uintptr_t i0 = reinterpret_cast<uintptr_t>(d_in), o0 = reinterpret_cast<uintptr_t>(d_out);
+  const uintptr_t bytes = (uintptr_t)nchan * (uintptr_t)nsamp;
+  if (i0 != o0 && i0 < o0 + bytes && o0 < i0 + bytes) return fail(SPS_ERR_INVALID_ARG);
+  sps::ZeroDmArgs a;
+  a.in = d_in;
+  a.out = d_out;
+  a.nsamp = nsamp;
+  a.nchan = nchan;
+  a.offset = offset;
+  a.aligned4 = (nsamp % 4 == 0) && (i0 % 4 == 0) && (o0 % 4 == 0);
+  if (sps::launch_zero_dm(a, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  return ok();
+}
+
 void sps_dedisp_destroy(sps_dedisp* k) {
   if (!k) return;
   if (k->pending) (void)hipEventSynchronize(k->done);

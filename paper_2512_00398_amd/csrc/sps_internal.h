@@ -99,6 +99,16 @@ struct DedispArgs {
   float* out;             // [ndm][nsamp_out]
 };
 
+// Zero-DM filter: in and out [nchan][nsamp] uint8 (may be the same array).
+struct ZeroDmArgs {
+  const uint8_t* in;
+  uint8_t* out;
+  int64_t nsamp;
+  int32_t nchan;
+  int32_t offset;
+  int32_t aligned4;  // 4-byte words: nsamp % 4 == 0 and both pointers 4-byte aligned
+};
+
 struct DetectArgs {
   const float* x;
   int64_t ld;
@@ -213,6 +223,7 @@ hipError_t launch_fixup(const DetectArgs& a, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 hipError_t launch_row_mad(const RowMadArgs& a, hipStream_t s);
 hipError_t launch_dedisp(const DedispArgs& a, hipStream_t s);
+hipError_t launch_zero_dm(const ZeroDmArgs& a, hipStream_t s);
 hipError_t launch_validate(const float* x, int64_t n, float bound, uint32_t* bad, hipStream_t s);
 hipError_t launch_stream_fold(const StreamArgs& a, hipStream_t s);
 hipError_t launch_stream_advance(const StreamArgs& a, hipStream_t s);

@@ -78,6 +78,7 @@ EXPORTS = [
     ("sps_dedisp_nsamp_out", ctypes.c_int64, [_P]),
     ("sps_dedisp_run", ctypes.c_int, [_P, _P, _P, _P]),
     ("sps_dedisp_destroy", None, [_P]),
+    ("sps_zero_dm", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P, _P]),
     ("sps_last_error", ctypes.c_int, []),
     ("sps_error_string", ctypes.c_char_p, [ctypes.c_int]),
 ]
@@ -448,6 +449,23 @@ def dedisp_delays(freqs_mhz, f_ref_mhz: float, tsamp_s: float, dms) -> np.ndarra
                                   out.ctypes.data)
     if rc:
         raise SpsError(rc, "sps_dedisp_delays")
+    return out
+
+
+def zero_dm(fil, offset: int, out=None, stream=None):
+    """Broadband (zero-DM) RFI excision of a uint8 GPU filterbank [nchan][nsamp]
+    (sps_zero_dm); out may be fil itself (in place) or a new tensor."""
+    import torch
+    if fil.dtype != torch.uint8 or fil.dim() != 2 or not fil.is_contiguous():
+        raise ValueError("filterbank must be a contiguous uint8 GPU tensor [nchan][nsamp]")
+    if out is None:
+        out = torch.empty_like(fil)
+    if out.dtype != torch.uint8 or out.shape != fil.shape or not out.is_contiguous():
+        raise ValueError("out must match the filterbank")
+    rc = load().sps_zero_dm(fil.data_ptr(), fil.shape[0], fil.shape[1], int(offset), _stream_handle(stream),
+                            out.data_ptr())
+    if rc:
+        raise SpsError(rc, "sps_zero_dm")
     return out
 
 

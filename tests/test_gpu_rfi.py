@@ -1,0 +1,97 @@
+"""GPU parity of broadband (zero-DM) RFI excision against the oracle (exact bytes)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dedisp_oracle as dd
+from oracle import rfi_oracle as ro
+from synth import filterbank as fb
+from parity import exact_equal
+
+pytestmark = pytest.mark.gpu
+
+
+def sps():
+    from paper_2512_00398_amd import sps as m
+    return m
+
+
+def run(fil, offset, in_place=False):
+    import torch
+    m = sps()
+    x = torch.from_numpy(np.ascontiguousarray(fil)).cuda()
+    out = m.zero_dm(x, offset, out=x if in_place else None)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("nchan,nsamp,offset", [(1, 1, 0), (3, 7, 255), (64, 1000, 64), (100, 1003, 30),
+                                                (1000, 4096, 128), (7, 257, 1)])
+def test_zero_dm_parity(nchan, nsamp, offset):
+    print("zero-dm case nchan=%d nsamp=%d offset=%d" % (nchan, nsamp, offset), flush=True)
+    sys.stdout.flush()
+    rng = np.random.default_rng(nchan * 7 + nsamp)
+    fil = rng.integers(0, 256, size=(nchan, nsamp)).astype(np.uint8)
+    ref = ro.zero_dm(fil, offset)
+    assert np.array_equal(run(fil, offset), ref)
+    assert np.array_equal(run(fil, offset, in_place=True), ref)
+
+
+def test_overlapping_output_rejected():
+    import torch
+    m = sps()
+    base = torch.zeros(500, dtype=torch.uint8, device="cuda")
+    x = base[:400].view(4, 100)
+    with pytest.raises(m.SpsError):
+        m.zero_dm(x, 0, out=base[50:450].view(4, 100))  # same size, shifted by 50 bytes: overlaps
+    with pytest.raises(m.SpsError):
+        m.zero_dm(x, 300)
+
+
+def test_zero_dm_before_dedispersion_removes_broadband_burst():
+    # an undispersed burst in every channel shows up at every trial DM; after
+    # the zero-DM filter the dedispersed block has no trace of it, and the
+    # dispersed pulse is still the brightest candidate
+    import torch
+    m = sps()
+    nchan, ndm = 128, 48
+    f, fref = fb.band(nchan)
+    dms = np.linspace(0, 500, ndm).astype(np.float32)
+    tab = m.dedisp_delays(f, fref, 98.304e-6, dms)
+    nin = 30000 + int(tab.max())
+    fil = fb.filterbank(nchan, nin, seed=21, pulses=[(12000, 8, 14)], tracks=tab[[30]])
+    burst = fil.astype(np.int64)
+    burst[:, 20000:20016] += 60  # broadband, DM 0
+    fil = np.minimum(burst, 255).astype(np.uint8)
+    x = torch.from_numpy(fil).cuda()
+    m.zero_dm(x, 64, out=x)
+    with m.Dedisperser(nchan, nin, tab) as k:
+        blk = k.run(x)
+        with m.Plan(ndm, k.nsamp_out, 64, 4096, 7.0) as p:
+            cands, ncand = p.alloc_cands()
+            p.search(blk, cands, ncand)
+            torch.cuda.synchronize()
+            got = m.cands_to_numpy(cands, ncand, p.max_cands)
+    clean = ro.zero_dm(fil, 64)
+    assert np.array_equal(x.cpu().numpy(), clean)
+    ref = oracle.search(dd.dedisperse(clean, tab.astype(np.int64)).astype(np.float32), 64, 4096, 7.0)
+    assert exact_equal(got, ref)
+    best = ref[np.argmax(ref["snr"])]
+    assert best["dm_idx"] == 30 and abs(int(best["sample"]) - 12000) <= 8
+    # nothing from the burst: no candidate near the burst time at DM 0
+    near = ref[(ref["dm_idx"] == 0) & (np.abs(ref["sample"].astype(np.int64) - 20000) < 64)]
+    assert near.size == 0
+
+
+def test_zero_dm_full_size():
+    # the benchmark filterbank shape: 1024 channels x 298,529 samples
+    import torch
+    m = sps()
+    nchan, nsamp = 1024, 298529
+    print("zero-dm full size %d x %d" % (nchan, nsamp), flush=True)
+    fil = fb.filterbank(nchan, nsamp, seed=31)
+    fil[:, 5000:5003] = 250
+    out = run(fil, 64)
+    assert np.array_equal(out, ro.zero_dm(fil, 64))
