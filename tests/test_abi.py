@@ -128,3 +128,32 @@ def test_header_is_plain_c_and_links(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True)
     assert out.returncode == 0, out
     assert "domain" in out.stdout
+
+
+def test_producer_entry_points_validate_without_device():
+    # argument checks of dedispersion and zero-DM excision come before any device call
+    from paper_2512_00398_amd import sps
+    import numpy as np
+    lib = sps.load()
+    assert lib.sps_dedisp_create(0, 100, 1, None) is None
+    assert lib.sps_last_error() == sps.SPS_ERR_INVALID_ARG
+    tab = np.array([[0, 5, 120]], dtype=np.int32)  # largest delay 120 >= nsamp_in 100
+    assert lib.sps_dedisp_create(3, 100, 1, tab.ctypes.data) is None
+    assert lib.sps_last_error() == sps.SPS_ERR_INVALID_ARG
+    neg = np.array([[0, -1, 3]], dtype=np.int32)
+    assert lib.sps_dedisp_create(3, 100, 1, neg.ctypes.data) is None
+    assert lib.sps_dedisp_nsamp_out(None) == -1
+    assert lib.sps_dedisp_run(None, None, None, None) == sps.SPS_ERR_INVALID_ARG
+    lib.sps_dedisp_destroy(None)
+    assert lib.sps_zero_dm(None, 4, 100, 0, None, None) == sps.SPS_ERR_INVALID_ARG
+    lib.sps_cluster_destroy(None)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr
