@@ -15,6 +15,17 @@ strategy, not the estimator, so the reading is this project's:
    nchan) / (2 * nchan)).
 2. Output: O[f, t] = min(255, max(0, I[f, t] - z_t + offset)) with the
    caller's integer offset in [0, 255] (the level the filtered data sit at).
+
+Narrowband interference raises the power of a few channels. Reading for that
+half of the strategy:
+
+3. Per channel f over the chunk: mu_f = lower median of I[f, :] and sigma_f =
+   lower median of |I[f, t] - mu_f| (rank floor((n-1)/2) of the sorted values).
+4. Across channels: M = lower median of sigma_f and S = lower median of
+   |sigma_f - M|; channel f is flagged iff sigma_f > M + k * S for the caller's
+   integer k >= 0.
+5. A flagged channel is replaced by its median: O[f, t] = mu_f for every t;
+   the other channels are unchanged.
 """
 from __future__ import annotations
 
@@ -38,3 +49,37 @@ def zero_dm(fil: np.ndarray, offset: int) -> np.ndarray:
     z = zero_dm_level(fil)
     out = fil.astype(np.int64) - z[None, :] + int(offset)
     return np.clip(out, 0, 255).astype(np.uint8)
+
+
+def _lower_median(v: np.ndarray) -> int:
+    v = np.asarray(v, dtype=np.int64)
+    r = (v.size - 1) // 2
+    return int(np.partition(v, r)[r])
+
+
+def channel_stats(fil: np.ndarray):
+    """Reading 3: int64 arrays (mu_f, sigma_f) over the channels of a uint8 [nchan][nsamp] filterbank."""
+    fil = np.asarray(fil)
+    if fil.dtype != np.uint8 or fil.ndim != 2:
+        raise ValueError("filterbank must be uint8 [nchan][nsamp]")
+    mu = np.array([_lower_median(row) for row in fil], dtype=np.int64)
+    sg = np.array([_lower_median(np.abs(row.astype(np.int64) - m)) for row, m in zip(fil, mu)], dtype=np.int64)
+    return mu, sg
+
+
+def channel_flags(sigma: np.ndarray, k: int) -> np.ndarray:
+    """Reading 4: bool flags from the channels' MADs."""
+    if int(k) < 0:
+        raise ValueError("k must be >= 0")
+    M = _lower_median(sigma)
+    S = _lower_median(np.abs(np.asarray(sigma, dtype=np.int64) - M))
+    return np.asarray(sigma) > M + int(k) * S
+
+
+def channel_mask(fil: np.ndarray, k: int):
+    """Readings 3-5: (filtered uint8 filterbank, mu, sigma, flags)."""
+    mu, sg = channel_stats(fil)
+    fl = channel_flags(sg, k)
+    out = np.array(fil, dtype=np.uint8, copy=True)
+    out[fl] = mu[fl, None].astype(np.uint8)
+    return out, mu, sg, fl

@@ -53,3 +53,40 @@ def test_clipping_and_offset_range():
     assert out.tolist() == [[0, 127], [127, 0]]
     with pytest.raises(ValueError):
         ro.zero_dm(fil, 256)
+
+
+def test_channel_stats_brute_force():
+    rng = np.random.default_rng(7)
+    fil = rng.integers(0, 256, size=(6, 41)).astype(np.uint8)
+    fil[2] = rng.integers(100, 103, size=41)
+    mu, sg = ro.channel_stats(fil)
+    for f in range(6):
+        row = sorted(int(v) for v in fil[f])
+        m = row[20]
+        assert mu[f] == m
+        assert sg[f] == sorted(abs(v - m) for v in row)[20]
+
+
+def test_noisy_channels_are_flagged_and_replaced_by_their_median():
+    rng = np.random.default_rng(8)
+    fil = np.clip(np.rint(rng.normal(64, 6, size=(64, 3000))), 0, 255).astype(np.uint8)
+    bad = [5, 40, 41]
+    for f in bad:  # narrowband interference: strongly fluctuating power
+        fil[f] = np.clip(np.rint(rng.normal(90, 40, size=3000)), 0, 255).astype(np.uint8)
+    out, mu, sg, fl = ro.channel_mask(fil, 3)
+    assert sorted(np.flatnonzero(fl).tolist()) == bad
+    for f in bad:
+        assert np.all(out[f] == mu[f])
+    keep = np.setdiff1d(np.arange(64), bad)
+    assert np.array_equal(out[keep], fil[keep])
+
+
+def test_channel_mask_closed_cases():
+    # identical channels: S = 0 and no channel exceeds M; nothing is flagged
+    fil = np.tile(np.arange(50, dtype=np.uint8), (8, 1))
+    out, _, _, fl = ro.channel_mask(fil, 0)
+    assert not fl.any() and np.array_equal(out, fil)
+    # k = 0: every channel above the median MAD is flagged
+    fil = np.stack([np.tile(np.array([100 - d, 100, 100 + d], dtype=np.uint8), 7) for d in (1, 2, 3, 4, 5)])
+    _, _, sg, fl = ro.channel_mask(fil, 0)
+    assert sg.tolist() == [1, 2, 3, 4, 5] and fl.tolist() == [False, False, False, True, True]
