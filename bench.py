@@ -229,6 +229,16 @@ def bench_dedisp(args):
     ez1.record(stream)
     torch.cuda.synchronize()
     zms = ez0.elapsed_time(ez1) / args.steps
+    # narrowband excision (channel statistics, flags, replacement) into the same second buffer
+    st = torch.empty((nchan, 3), dtype=torch.uint8, device="cuda")
+    sps.chan_mask(fd, 4, out=fz, stats=st, stream=stream)
+    torch.cuda.synchronize()
+    ez0.record(stream)
+    for _ in range(args.steps):
+        sps.chan_mask(fd, 4, out=fz, stats=st, stream=stream)
+    ez1.record(stream)
+    torch.cuda.synchronize()
+    mms = ez0.elapsed_time(ez1) / args.steps
     # the pipeline: zero-DM excision, dedispersion, then the search of its output
     plan = sps.Plan(ndm, nout, 4096, 16384, 6.0)
     cands, ncand = plan.alloc_cands()
@@ -271,6 +281,7 @@ def bench_dedisp(args):
         "kernel_ms": kms,
         "zero_dm": {"ms": zms, "algorithmic_GBps": 2.0 * nchan * nin / (zms * 1e-3) / 1e9,
                     "note": "filterbank read once and written once (algorithmic); the kernel reads it twice"},
+        "chan_mask": {"ms": mms, "k": 4, "flagged": int(st[:, 2].sum().item())},
         "pipeline": "zero-DM excision + dedispersion + search", "pipeline_ms_per_chunk": pipe_ms,
         "pipeline_candidates": n, "cpu_baseline": cpu}))
 

@@ -364,6 +364,21 @@ typedef struct sps_dedisp sps_dedisp;
 int sps_zero_dm(const uint8_t* d_in, int32_t nchan, int64_t nsamp, int32_t offset, hipStream_t stream,
                 uint8_t* d_out);
 
+/* ---- Narrowband RFI excision (Heimdall++ Section II-B, "RFI Mitigation").
+ * sps_chan_mask: d_in and d_out as for sps_zero_dm (d_out may equal d_in).
+ *   For each channel f over the chunk, mu_f = lower median of in[f][:] and
+ *   sigma_f = lower median of |in[f][t] - mu_f| (rank (nsamp-1)/2); across
+ *   channels M = lower median of sigma_f and S = lower median of
+ *   |sigma_f - M| (rank (nchan-1)/2). Channel f is flagged iff
+ *   sigma_f > M + k * S, and a flagged channel is written as mu_f at every
+ *   sample; the others are copied. d_stats is a device byte array
+ *   [nchan][3] receiving (mu_f, sigma_f, flag); it must not overlap the
+ *   filterbanks. nchan in [1, 65536], nsamp in [1, INT32_MAX - 8192],
+ *   k >= 0. Asynchronous on `stream`; SPS_ERR_INVALID_ARG (bad sizes, NULL
+ *   or overlapping buffers), SPS_ERR_HIP (launch failure). */
+int sps_chan_mask(const uint8_t* d_in, int32_t nchan, int64_t nsamp, int32_t k, hipStream_t stream, uint8_t* d_out,
+                  uint8_t* d_stats);
+
 int sps_dedisp_delays(int32_t nchan, const double* freqs_mhz, double f_ref_mhz, double tsamp_s, int32_t ndm,
                       const float* dms, int32_t* delays);
 sps_dedisp* sps_dedisp_create(int32_t nchan, int64_t nsamp_in, int32_t ndm, const int32_t* delays);

@@ -1643,6 +1643,28 @@ int sps_zero_dm(const uint8_t* d_in, int32_t nchan, int64_t nsamp, int32_t offse
   return ok();
 }
 
+int sps_chan_mask(const uint8_t* d_in, int32_t nchan, int64_t nsamp, int32_t k, hipStream_t stream, uint8_t* d_out,
+                  uint8_t* d_stats) {
+  if (!d_in || !d_out || !d_stats || nchan < 1 || nchan > 65536 || nsamp < 1 || nsamp > (int64_t)INT32_MAX - 8192 ||
+      k < 0)
+    return fail(SPS_ERR_INVALID_ARG);
+  const uintptr_t i0 = reinterpret_cast<uintptr_t>(d_in), o0 = reinterpret_cast<uintptr_t>(d_out);
+  const uintptr_t s0 = reinterpret_cast<uintptr_t>(d_stats);
+  const uintptr_t bytes = (uintptr_t)nchan * (uintptr_t)nsamp, sbytes = 3 * (uintptr_t)nchan;
+  if (i0 != o0 && i0 < o0 + bytes && o0 < i0 + bytes) return fail(SPS_ERR_INVALID_ARG);
+  if ((s0 < i0 + bytes && i0 < s0 + sbytes) || (s0 < o0 + bytes && o0 < s0 + sbytes)) return fail(SPS_ERR_INVALID_ARG);
+  sps::ChanMaskArgs a;
+  a.in = d_in;
+  a.out = d_out;
+  a.stats = d_stats;
+  a.nsamp = nsamp;
+  a.nchan = nchan;
+  a.k = k;
+  a.aligned4 = (nsamp % 4 == 0) && (i0 % 4 == 0) && (o0 % 4 == 0);
+  if (sps::launch_chan_mask(a, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  return ok();
+}
+
 void sps_dedisp_destroy(sps_dedisp* k) {
   if (!k) return;
   if (k->pending) (void)hipEventSynchronize(k->done);

@@ -109,6 +109,18 @@ struct ZeroDmArgs {
   int32_t aligned4;  // 4-byte words: nsamp % 4 == 0 and both pointers 4-byte aligned
 };
 
+// Narrowband channel mask: in/out [nchan][nsamp] uint8 (may be the same
+// array); stats [nchan][3] bytes: median, MAD, flag.
+struct ChanMaskArgs {
+  const uint8_t* in;
+  uint8_t* out;
+  uint8_t* stats;
+  int64_t nsamp;
+  int32_t nchan;
+  int32_t k;
+  int32_t aligned4;  // 4-byte words: nsamp % 4 == 0 and both pointers 4-byte aligned
+};
+
 struct DetectArgs {
   const float* x;
   int64_t ld;
@@ -224,6 +236,7 @@ hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 hipError_t launch_row_mad(const RowMadArgs& a, hipStream_t s);
 hipError_t launch_dedisp(const DedispArgs& a, hipStream_t s);
 hipError_t launch_zero_dm(const ZeroDmArgs& a, hipStream_t s);
+hipError_t launch_chan_mask(const ChanMaskArgs& a, hipStream_t s);
 hipError_t launch_validate(const float* x, int64_t n, float bound, uint32_t* bad, hipStream_t s);
 hipError_t launch_stream_fold(const StreamArgs& a, hipStream_t s);
 hipError_t launch_stream_advance(const StreamArgs& a, hipStream_t s);

@@ -1,5 +1,8 @@
-// sps_rfi.hip - broadband (zero-DM) RFI excision (Heimdall++, Section II-B,
-// "RFI Mitigation"): interference present in every channel at once is
+// sps_rfi.hip - RFI excision (Heimdall++, Section II-B, "RFI Mitigation").
+// Narrowband: channels whose lower MAD over the chunk exceeds the median of
+// the channels' MADs by k MADs of those MADs are replaced by their median
+// (exact byte order statistics from 256-bin histograms).
+// Broadband (zero-DM): interference present in every channel at once is
 // undispersed; each time sample's level across the band,
 // z_t = floor((2 * sum_f I[f][t] + nchan) / (2 * nchan)) (the channel mean
 // rounded half up), is subtracted from every channel and the caller's offset
@@ -78,7 +81,106 @@ __global__ __launch_bounds__(64 * kZdWaves) void k_zero_dm(ZeroDmArgs a) {
   }
 }
 
+// ---- narrowband: per-channel statistics, flags, replacement -----------------
+// Exact order statistics of bytes from a 256-bin histogram H with n values:
+// the lower median (rank (n-1)/2) and the lower MAD about it, found by
+// widening [mu - D, mu + D] until it holds more than the rank.
+__device__ void hist_median_mad(const uint32_t* H, uint32_t n, int& mu, int& mad) {
+  const uint32_t r = (n - 1) / 2;
+  uint32_t acc = 0;
+  int m = 0;
+  for (; m < 256; ++m) {
+    acc += H[m];
+    if (acc > r) break;
+  }
+  uint32_t cnt = H[m];
+  int d = 0;
+  while (cnt <= r) {
+    ++d;
+    if (m - d >= 0) cnt += H[m - d];
+    if (m + d <= 255) cnt += H[m + d];
+  }
+  mu = m;
+  mad = d;
+}
+
+// One workgroup per channel: byte histogram of the row (one sub-histogram
+// per wave against same-bin contention), then its median and MAD.
+__global__ __launch_bounds__(256) void k_chan_stats(ChanMaskArgs a) {
+  __shared__ uint32_t h[4][256];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int f = blockIdx.x;
+  for (int b = tid; b < 4 * 256; b += 256) (&h[0][0])[b] = 0;
+  __syncthreads();
+  const uint8_t* row = a.in + (int64_t)f * a.nsamp;
+  for (int64_t i = 4 * (int64_t)tid; i < a.nsamp; i += 1024) {
+    if (a.aligned4 && i + 3 < a.nsamp) {
+      const uint32_t w = *reinterpret_cast<const uint32_t*>(row + i);
+      atomicAdd(&h[wave][w & 0xFFu], 1u);
+      atomicAdd(&h[wave][(w >> 8) & 0xFFu], 1u);
+      atomicAdd(&h[wave][(w >> 16) & 0xFFu], 1u);
+      atomicAdd(&h[wave][w >> 24], 1u);
+    } else {
+      for (int q = 0; q < 4; ++q)
+        if (i + q < a.nsamp) atomicAdd(&h[wave][row[i + q]], 1u);
+    }
+  }
+  __syncthreads();
+  h[0][tid] += h[1][tid] + h[2][tid] + h[3][tid];
+  __syncthreads();
+  if (tid == 0) {
+    int mu, mad;
+    hist_median_mad(h[0], (uint32_t)a.nsamp, mu, mad);
+    a.stats[3 * (int64_t)f] = (uint8_t)mu;
+    a.stats[3 * (int64_t)f + 1] = (uint8_t)mad;
+  }
+}
+
+// One workgroup: median M and MAD S of the channels' MADs (bytes again),
+// then the flags sigma_f > M + k * S.
+__global__ __launch_bounds__(256) void k_chan_flags(ChanMaskArgs a) {
+  __shared__ uint32_t h[256];
+  __shared__ int ms[2];
+  const int tid = threadIdx.x;
+  h[tid] = 0;
+  __syncthreads();
+  for (int f = tid; f < a.nchan; f += 256) atomicAdd(&h[a.stats[3 * (int64_t)f + 1]], 1u);
+  __syncthreads();
+  if (tid == 0) hist_median_mad(h, (uint32_t)a.nchan, ms[0], ms[1]);
+  __syncthreads();
+  const int64_t lim = (int64_t)ms[0] + (int64_t)a.k * ms[1];
+  for (int f = tid; f < a.nchan; f += 256) a.stats[3 * (int64_t)f + 2] = (int64_t)a.stats[3 * (int64_t)f + 1] > lim;
+}
+
+// Flagged channels take their median; the others are copied (nothing to do in place).
+__global__ __launch_bounds__(256) void k_chan_apply(ChanMaskArgs a) {
+  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (i >= a.nsamp) return;
+  for (int f = blockIdx.y; f < a.nchan; f += gridDim.y) {
+    const bool flag = a.stats[3 * (int64_t)f + 2] != 0;
+    if (!flag && a.in == a.out) continue;
+    const int64_t at = (int64_t)f * a.nsamp + i;
+    const uint8_t mu = a.stats[3 * (int64_t)f];
+    if (a.aligned4 && i + 3 < a.nsamp) {
+      const uint32_t v = flag ? 0x01010101u * mu : *reinterpret_cast<const uint32_t*>(a.in + at);
+      *reinterpret_cast<uint32_t*>(a.out + at) = v;
+    } else {
+      for (int q = 0; q < 4; ++q)
+        if (i + q < a.nsamp) a.out[at + q] = flag ? mu : a.in[at + q];
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_chan_mask(const ChanMaskArgs& a, hipStream_t s) {
+  if (a.nsamp <= 0 || a.nchan <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_chan_stats, dim3((unsigned)a.nchan), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_chan_flags, dim3(1), dim3(256), 0, s, a);
+  const unsigned gx = (unsigned)((a.nsamp + 1023) / 1024), gy = (unsigned)min(a.nchan, 65535);
+  hipLaunchKernelGGL(k_chan_apply, dim3(gx, gy), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_zero_dm(const ZeroDmArgs& a, hipStream_t s) {
   if (a.nsamp <= 0 || a.nchan <= 0) return hipSuccess;

@@ -79,6 +79,7 @@ EXPORTS = [
     ("sps_dedisp_run", ctypes.c_int, [_P, _P, _P, _P]),
     ("sps_dedisp_destroy", None, [_P]),
     ("sps_zero_dm", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P, _P]),
+    ("sps_chan_mask", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P, _P, _P]),
     ("sps_last_error", ctypes.c_int, []),
     ("sps_error_string", ctypes.c_char_p, [ctypes.c_int]),
 ]
@@ -467,6 +468,26 @@ def zero_dm(fil, offset: int, out=None, stream=None):
     if rc:
         raise SpsError(rc, "sps_zero_dm")
     return out
+
+
+def chan_mask(fil, k: int, out=None, stats=None, stream=None):
+    """Narrowband RFI excision of a uint8 GPU filterbank [nchan][nsamp]
+    (sps_chan_mask); returns (out, stats) with stats uint8 [nchan][3] =
+    (median, MAD, flag) per channel. out may be fil itself (in place)."""
+    import torch
+    if fil.dtype != torch.uint8 or fil.dim() != 2 or not fil.is_contiguous():
+        raise ValueError("filterbank must be a contiguous uint8 GPU tensor [nchan][nsamp]")
+    if out is None:
+        out = torch.empty_like(fil)
+    if out.dtype != torch.uint8 or out.shape != fil.shape or not out.is_contiguous():
+        raise ValueError("out must match the filterbank")
+    if stats is None:
+        stats = torch.empty((fil.shape[0], 3), dtype=torch.uint8, device=fil.device)
+    rc = load().sps_chan_mask(fil.data_ptr(), fil.shape[0], fil.shape[1], int(k), _stream_handle(stream),
+                              out.data_ptr(), stats.data_ptr())
+    if rc:
+        raise SpsError(rc, "sps_chan_mask")
+    return out, stats
 
 
 class Dedisperser:

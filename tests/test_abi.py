@@ -157,3 +157,9 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_chan_mask_validates_without_device():
+    from paper_2512_00398_amd import sps
+    lib = sps.load()
+    assert lib.sps_chan_mask(None, 4, 100, 0, None, None, None) == sps.SPS_ERR_INVALID_ARG

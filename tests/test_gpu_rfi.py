@@ -95,3 +95,48 @@ def test_zero_dm_full_size():
     fil[:, 5000:5003] = 250
     out = run(fil, 64)
     assert np.array_equal(out, ro.zero_dm(fil, 64))
+
+
+def run_mask(fil, k, in_place=False):
+    import torch
+    m = sps()
+    x = torch.from_numpy(np.ascontiguousarray(fil)).cuda()
+    out, st = m.chan_mask(x, k, out=x if in_place else None)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("nchan,nsamp,k", [(1, 1, 0), (2, 5, 0), (64, 3000, 3), (37, 1001, 2), (300, 4096, 0)])
+def test_chan_mask_parity(nchan, nsamp, k):
+    print("chan-mask case nchan=%d nsamp=%d k=%d" % (nchan, nsamp, k), flush=True)
+    rng = np.random.default_rng(nchan + 3 * nsamp)
+    fil = np.clip(np.rint(rng.normal(64, 6, size=(nchan, nsamp))), 0, 255).astype(np.uint8)
+    for f in range(0, nchan, 7):  # noisy channels
+        fil[f] = np.clip(np.rint(rng.normal(90, 40, size=nsamp)), 0, 255).astype(np.uint8)
+    ref, mu, sg, fl = ro.channel_mask(fil, k)
+    for in_place in (False, True):
+        out, st = run_mask(fil, k, in_place)
+        assert np.array_equal(st[:, 0], mu) and np.array_equal(st[:, 1], sg)
+        assert np.array_equal(st[:, 2].astype(bool), fl)
+        assert np.array_equal(out, ref)
+
+
+def test_chan_mask_then_zero_dm_full_size():
+    # the benchmark filterbank shape with 20 noisy channels: mask, then zero-DM, as one pre-dedispersion pass
+    import torch
+    m = sps()
+    nchan, nsamp = 1024, 298529
+    print("chan-mask full size %d x %d" % (nchan, nsamp), flush=True)
+    fil = fb.filterbank(nchan, nsamp, seed=41)
+    rng = np.random.default_rng(41)
+    bad = rng.choice(nchan, size=20, replace=False)
+    for f in bad:
+        fil[f] = np.clip(np.rint(rng.normal(100, 50, size=nsamp)), 0, 255).astype(np.uint8)
+    ref, mu, sg, fl = ro.channel_mask(fil, 4)
+    assert set(np.flatnonzero(fl).tolist()) == set(bad.tolist())
+    x = torch.from_numpy(fil).cuda()
+    out, st = m.chan_mask(x, 4, out=x)
+    z = m.zero_dm(out, 64)
+    torch.cuda.synchronize()
+    assert np.array_equal(st.cpu().numpy()[:, 2].astype(bool), fl)
+    assert np.array_equal(z.cpu().numpy(), ro.zero_dm(ref, 64))
