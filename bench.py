@@ -42,9 +42,9 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md,
     # profiles/dedisp_1024ch_1024dm_2p18.md
-    "detect": ("a2bad7622dcfb8ff", (2237780 * 2 + 170197) * 1024),
-    "block_stats": ("45d0f5954077a9e5", (4349792 * 2 + 137106) * 1024),
-    "dedisp": ("bf3ccaf5dfb701ca", (3439633 * 2 + 1048576) * 1024),
+    "detect": ("0e43ccaf427fa78b", (2237779 * 2 + 170183) * 1024),
+    "block_stats": ("90fcfbe7dbc2b3b5", (4349797 * 2 + 137109) * 1024),
+    "dedisp": ("9e76311a505501bf", (3441044 * 2 + 1048576) * 1024),
 }
 
 
