@@ -1495,7 +1495,19 @@ int sps_dedisp_delays(int32_t nchan, const double* freqs_mhz, double f_ref_mhz, 
   return ok();
 }
 
+static sps_dedisp* dedisp_create(int32_t nchan, int64_t nsamp_in, int32_t ndm, const int32_t* delays);
+
 sps_dedisp* sps_dedisp_create(int32_t nchan, int64_t nsamp_in, int32_t ndm, const int32_t* delays) {
+  // the host tables are std::vector: an allocation failure must not cross the C boundary
+  try {
+    return dedisp_create(nchan, nsamp_in, ndm, delays);
+  } catch (const std::bad_alloc&) {
+    fail(SPS_ERR_OOM);
+    return nullptr;
+  }
+}
+
+static sps_dedisp* dedisp_create(int32_t nchan, int64_t nsamp_in, int32_t ndm, const int32_t* delays) {
   if (nchan < 1 || nchan > 65536 || ndm < 1 || nsamp_in < 1 || nsamp_in > (int64_t)INT32_MAX - 8192 || !delays) {
     fail(SPS_ERR_INVALID_ARG);
     return nullptr;
