@@ -42,9 +42,9 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md,
     # profiles/dedisp_1024ch_1024dm_2p18.md
-    "detect": ("0e43ccaf427fa78b", (2237779 * 2 + 170183) * 1024),
-    "block_stats": ("90fcfbe7dbc2b3b5", (4349797 * 2 + 137109) * 1024),
-    "dedisp": ("9e76311a505501bf", (3441044 * 2 + 1048576) * 1024),
+    "detect": ("a887b5a488378cb8", (2237779 * 2 + 170185) * 1024),
+    "block_stats": ("2e9d5d2d1e7f0a73", (4349788 * 2 + 137113) * 1024),
+    "dedisp": ("a0a762ea61972dd1", (3436542 * 2 + 1048576) * 1024),
 }
 
 
