@@ -46,6 +46,16 @@ design notes):
     ``MAD_row`` = lower median of ``|r_t - c|`` over the whole row, where
     ``c`` is the lower median of ``r_t``; items 6-7 then use it in place of
     ``MAD_{k*}``. The medians ``m_k`` are unchanged.
+11. Per-width re-normalisation variant (a plan option; Section II-B's
+    normalisation read as a scale for every filtered series, the way
+    Heimdall re-normalises each boxcar output): the residual and boxcar sums
+    of items 5 are unchanged; for each row and width w the filtered series
+    ``T_w = {S_w(i) : 0 <= i <= N - w}`` gets its own robust scale,
+    ``c_w`` = lower median of ``T_w`` and ``MAD_w`` = lower median of
+    ``|S_w(i) - c_w|``, and item 6 becomes ``snr = S_w(i) / (K * MAD_w)`` in
+    IEEE double (no sqrt(w): ``MAD_w`` already measures the filtered series);
+    a width with ``MAD_w = 0`` has no above positions. The medians ``m_k``
+    are unchanged; items 7-8 are unchanged.
 """
 from __future__ import annotations
 
@@ -123,6 +133,26 @@ def row_mad(r: np.ndarray) -> int:
     return lower_median(np.abs(r - c))
 
 
+def width_mad(sw: np.ndarray) -> Tuple[int, int]:
+    """Reading 11: lower median c_w of the filtered series and its lower MAD about c_w (0, 0 if empty)."""
+    if sw.size == 0:
+        return 0, 0
+    c = lower_median(sw)
+    return c, lower_median(np.abs(sw - c))
+
+
+def snr_and_above_width(sw: np.ndarray, mad_w: int, theta: float) -> Tuple[np.ndarray, np.ndarray]:
+    """Reading 11: FP64 S/N against the width's own scale, S_w(i) / (K * MAD_w); strict threshold.
+
+    A width with MAD_w = 0 has no above positions (snr NaN)."""
+    if mad_w <= 0:
+        return np.full(sw.size, np.nan), np.zeros(sw.size, dtype=bool)
+    den = K_MAD * float(mad_w)
+    snr = sw.astype(np.float64) / den
+    th = float(np.float32(theta))
+    return snr, snr > th
+
+
 def boxcar(r: np.ndarray, w: int) -> np.ndarray:
     """Reading 5, second half: S_w(i) = sum of r over [i, i+w), i = 0 .. N-w (matched filter)."""
     n = r.size
@@ -169,8 +199,11 @@ def peaks(above: np.ndarray, snr: np.ndarray) -> List[Tuple[int, float]]:
 
 
 def search_row(x_row: np.ndarray, dm_idx: int, max_width: int, baseline_len: int, theta: float,
-               stride: int = BLOCK_STRIDE, with_stats: bool = False, lead: int = 0, row_norm: bool = False):
+               stride: int = BLOCK_STRIDE, with_stats: bool = False, lead: int = 0, row_norm: bool = False,
+               width_norm: bool = False):
     """Stages of one DM trial in the paper's order: baseline, normalise, filter, detect."""
+    if row_norm and width_norm:
+        raise ValueError("row_norm and width_norm are alternative readings")
     m, mad = block_median_mad(x_row, baseline_len, stride, lead)
     r = residual(x_row, m, stride)
     if row_norm:
@@ -180,7 +213,10 @@ def search_row(x_row: np.ndarray, dm_idx: int, max_width: int, baseline_len: int
         sw = boxcar(r, w)
         if sw.size == 0:
             continue
-        snr, above = snr_and_above(sw, mad, w, theta, stride)
+        if width_norm:
+            snr, above = snr_and_above_width(sw, width_mad(sw)[1], theta)
+        else:
+            snr, above = snr_and_above(sw, mad, w, theta, stride)
         for j, s in peaks(above, snr):
             cands.append((j, dm_idx, w, s))
     arr = np.array(cands, dtype=[("sample", "<i8"), ("dm_idx", "<u4"), ("width", "<u4"), ("snr", "<f8")])
@@ -193,6 +229,19 @@ def search_row(x_row: np.ndarray, dm_idx: int, max_width: int, baseline_len: int
     return out
 
 
+def width_stats(x_row: np.ndarray, max_width: int, baseline_len: int, stride: int = BLOCK_STRIDE,
+                lead: int = 0) -> Tuple[np.ndarray, np.ndarray]:
+    """Reading 11's statistics of one row: c_w and MAD_w for every width (int64 arrays)."""
+    m, _ = block_median_mad(x_row, baseline_len, stride, lead)
+    r = residual(x_row, m, stride)
+    cs, ms = [], []
+    for w in widths(max_width):
+        c, d = width_mad(boxcar(r, w))
+        cs.append(c)
+        ms.append(d)
+    return np.array(cs, dtype=np.int64), np.array(ms, dtype=np.int64)
+
+
 def sort_cands(c: np.ndarray) -> np.ndarray:
     """Canonical order (dm_idx, width, sample): candidate order is not part of the result."""
     if c.size == 0:
@@ -203,14 +252,14 @@ def sort_cands(c: np.ndarray) -> np.ndarray:
 def search(block: np.ndarray, max_width: int, baseline_len: int, theta: float,
            rows: Optional[Iterable[int]] = None, stride: int = BLOCK_STRIDE,
            row_ids: Optional[Sequence[int]] = None, with_stats: bool = False, centered: bool = False,
-           row_norm: bool = False):
+           row_norm: bool = False, width_norm: bool = False):
     """Search every row of ``block`` ([ndm][N]); candidates sorted (dm, width, sample).
 
     ``rows`` restricts the search to those rows of ``block``; ``row_ids``
     gives the DM index reported for each row of ``block`` (default: the row's
     position). With ``with_stats`` also returns int64 ``m`` and ``mad`` of
-    shape ``[len(rows)][ceil(N/S)]``. ``centered`` and ``row_norm`` select
-    readings 9 and 10.
+    shape ``[len(rows)][ceil(N/S)]``. ``centered``, ``row_norm`` and
+    ``width_norm`` select readings 9, 10 and 11.
     """
     block = np.asarray(block)
     if block.ndim != 2:
@@ -220,7 +269,8 @@ def search(block: np.ndarray, max_width: int, baseline_len: int, theta: float,
     for r in rr:
         d = r if row_ids is None else int(row_ids[r])
         c, m, mad = search_row(block[r], d, max_width, baseline_len, theta, stride, with_stats=True,
-                               lead=window_lead(baseline_len, stride, centered), row_norm=row_norm)
+                               lead=window_lead(baseline_len, stride, centered), row_norm=row_norm,
+                               width_norm=width_norm)
         parts.append(c)
         ms.append(m)
         mads.append(mad)
