@@ -86,8 +86,9 @@ typedef struct sps_plan sps_plan;
 sps_plan* sps_plan_create(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baseline_len,
                           float snr_thresh);
 
-/* Free a plan and its device scratch. NULL-safe. Synchronises the device
- * first so that no enqueued work still uses the scratch. */
+/* Free a plan and its device scratch. NULL-safe. Waits first for the plan's
+ * last call (the end of its device work) so that no enqueued work still uses
+ * the scratch; work of other plans and streams is not waited for. */
 void sps_plan_destroy(sps_plan* plan);
 
 /*

@@ -42,6 +42,9 @@ struct sps_plan {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>* ev_pending;
   double stage_ms[SPS_NSTAGES];
   int64_t nsearch;
+  // end of the last call's device work (destroy and scratch regrowth wait for it)
+  hipEvent_t done;
+  bool pending;
 };
 
 namespace {
@@ -172,6 +175,41 @@ int64_t frag_need(const sps_plan* p) {
   return nseg > 1 ? (int64_t)p->ndm * p->nw * nseg : 0;
 }
 
+bool plan_shape_ok(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baseline_len, float snr_thresh) {
+  return ndm >= 1 && nsamp >= 1 && nsamp <= (int64_t)INT32_MAX - 8192 && is_pow2(max_width) &&
+         max_width <= SPS_MAX_WIDTH_LIMIT && baseline_len >= 1 && baseline_len <= SPS_MAX_BASELINE_LEN &&
+         std::isfinite(snr_thresh) && snr_thresh > 0.0f;
+}
+
+// Shape, widths and default tuning of a plan (no device memory, no events).
+void plan_params(sps_plan* p, int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baseline_len, float snr_thresh) {
+  std::memset(p, 0, sizeof(*p));
+  p->ndm = ndm;
+  p->nsamp = (int32_t)nsamp;
+  p->max_width = max_width;
+  p->baseline_len = baseline_len;
+  p->thresh = snr_thresh;
+  p->nblocks = (int32_t)((nsamp + sps::kStride - 1) / sps::kStride);
+  p->nw = 0;
+  for (int w = 1; w <= max_width; w <<= 1) {
+    p->sqrtw[p->nw] = std::sqrt((double)w);  // correctly rounded (IEEE sqrt)
+    ++p->nw;
+  }
+  p->max_cands = 1LL << 24;
+  p->hist_bins = 4096;
+}
+
+// Marks the end of a call's device work on `s` (plans with an event only).
+int finish(sps_plan* p, hipStream_t s) {
+  if (!p->done) return SPS_OK;
+  if (hipEventRecord(p->done, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return SPS_ERR_HIP;
+  }
+  p->pending = true;
+  return SPS_OK;
+}
+
 int64_t domain_bound(int32_t max_width) {
   const int64_t b = (int64_t)INT32_MAX / (2LL * (max_width > 0 ? max_width : 1));
   return b < (1LL << 24) - 1 ? b : (1LL << 24) - 1;
@@ -196,7 +234,7 @@ int ensure_frag(sps_plan* p) {
   const int64_t need = frag_need(p);
   if (need <= p->frag_cap) return SPS_OK;
   if (p->d_frag) {
-    (void)hipDeviceSynchronize();
+    if (p->pending) (void)hipEventSynchronize(p->done);
     (void)hipFree(p->d_frag);
     p->d_frag = nullptr;
     p->frag_cap = 0;
@@ -232,9 +270,7 @@ const char* sps_error_string(int code) {
 }
 
 sps_plan* sps_plan_create(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baseline_len, float snr_thresh) {
-  if (ndm < 1 || nsamp < 1 || nsamp > (int64_t)INT32_MAX - 8192 || !is_pow2(max_width) ||
-      max_width > SPS_MAX_WIDTH_LIMIT || baseline_len < 1 || baseline_len > SPS_MAX_BASELINE_LEN ||
-      !std::isfinite(snr_thresh) || !(snr_thresh > 0.0f)) {
+  if (!plan_shape_ok(ndm, nsamp, max_width, baseline_len, snr_thresh)) {
     fail(SPS_ERR_INVALID_ARG);
     return nullptr;
   }
@@ -243,7 +279,7 @@ sps_plan* sps_plan_create(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t
     fail(SPS_ERR_OOM);
     return nullptr;
   }
-  std::memset(p, 0, sizeof(*p));
+  plan_params(p, ndm, nsamp, max_width, baseline_len, snr_thresh);
   p->ev_free = new (std::nothrow) std::vector<hipEvent_t>();
   p->ev_pending = new (std::nothrow) std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>();
   if (!p->ev_free || !p->ev_pending) {
@@ -253,20 +289,8 @@ sps_plan* sps_plan_create(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t
     fail(SPS_ERR_OOM);
     return nullptr;
   }
-  p->ndm = ndm;
-  p->nsamp = (int32_t)nsamp;
-  p->max_width = max_width;
-  p->baseline_len = baseline_len;
-  p->thresh = snr_thresh;
-  p->nblocks = (int32_t)((nsamp + sps::kStride - 1) / sps::kStride);
-  p->nw = 0;
-  for (int w = 1; w <= max_width; w <<= 1) {
-    p->sqrtw[p->nw] = std::sqrt((double)w);  // correctly rounded (IEEE sqrt)
-    ++p->nw;
-  }
-  p->max_cands = 1LL << 24;
-  p->hist_bins = 4096;
-  if (hipGetDevice(&p->device) != hipSuccess) {
+  if (hipGetDevice(&p->device) != hipSuccess || hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
     delete p->ev_free;
     delete p->ev_pending;
     delete p;
@@ -292,7 +316,9 @@ sps_plan* sps_plan_create(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t
 
 void sps_plan_destroy(sps_plan* p) {
   if (!p) return;
-  (void)hipDeviceSynchronize();
+  // only this plan's own work uses its scratch: wait for its last call, not the device
+  if (p->pending) (void)hipEventSynchronize(p->done);
+  if (p->done) (void)hipEventDestroy(p->done);
   if (p->d_med) (void)hipFree(p->d_med);
   if (p->d_mad) (void)hipFree(p->d_mad);
   if (p->d_frag) (void)hipFree(p->d_frag);
@@ -403,7 +429,9 @@ int sps_block_stats(sps_plan* p, const float* d_series, hipStream_t stream, int3
   hipEvent_t e0 = mark(p, stream);
   const int rc = launch_stats(p, d_series, stream, d_median, d_mad);
   span(p, 0, e0, mark(p, stream));
-  return rc;
+  if (rc != SPS_OK) return rc;
+  if (finish(p, stream) != SPS_OK) return fail(SPS_ERR_HIP);
+  return ok();
 }
 
 }  // extern "C"
@@ -433,23 +461,19 @@ static int launch_stats(sps_plan* p, const float* d_series, hipStream_t stream, 
   return ok();
 }
 
-extern "C" {
-
-int sps_search(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand) {
-  if (!p || !d_series || !d_ncand || (!d_cands && p->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
-  sps::DetectArgs d;
-  d.seg_len = auto_detect_seg(p);
-  d.nseg = (p->nsamp + d.seg_len - 1) / d.seg_len;
-  if (d.nseg > 1 && (int64_t)p->ndm * p->nw * d.nseg > p->frag_cap) return fail(SPS_ERR_INVALID_ARG);
-  {
-    const int rc = check_domain(p, d_series, (int64_t)p->ndm * p->nsamp, stream);
-    if (rc != SPS_OK) return fail(rc);
-  }
+// The fused search of one block: counter reset, block statistics into
+// med/mad, fused detection (segments of seg_len positions; run summaries of
+// segment edges in frag when a row has several segments), fix-up.
+static int enqueue_search(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand* d_cands,
+                          uint32_t* d_ncand, int32_t* med, int32_t* mad, sps::RunSum* frag, int32_t seg_len) {
   hipEvent_t e0 = mark(p, stream);
-  if (sps::launch_zero_u32(d_ncand, 1, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  if (sps::launch_zero_u32(d_ncand, 1, stream) != hipSuccess) return SPS_ERR_HIP;
   hipEvent_t e1 = mark(p, stream);
-  if (launch_stats(p, d_series, stream, p->d_med, p->d_mad) != SPS_OK) return g_last_error;
+  if (launch_stats(p, d_series, stream, med, mad) != SPS_OK) return g_last_error;
   hipEvent_t e2 = mark(p, stream);
+  sps::DetectArgs d;
+  d.seg_len = seg_len;
+  d.nseg = (p->nsamp + seg_len - 1) / seg_len;
   d.x = d_series;
   d.ld = p->nsamp;
   d.hist = nullptr;
@@ -464,8 +488,8 @@ int sps_search(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand*
   d.nblocks = p->nblocks;
   d.nw = p->nw;
   d.maxw = p->max_width;
-  d.med = p->d_med;
-  d.mad = p->d_mad;
+  d.med = med;
+  d.mad = mad;
   d.theta = (double)p->thresh;
   for (int j = 0; j < sps::kMaxWidths; ++j) d.sqrtw[j] = j < p->nw ? p->sqrtw[j] : 0.0;
   d.rows = p->ndm;
@@ -473,16 +497,33 @@ int sps_search(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand*
   d.cands = d_cands;
   d.ncand = d_ncand;
   d.cap = (uint32_t)p->max_cands;
-  d.frag = p->d_frag;
-  if (sps::launch_detect(d, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  d.frag = frag;
+  if (sps::launch_detect(d, stream) != hipSuccess) return SPS_ERR_HIP;
   hipEvent_t e3 = mark(p, stream);
-  if (sps::launch_fixup(d, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  if (sps::launch_fixup(d, stream) != hipSuccess) return SPS_ERR_HIP;
   hipEvent_t e4 = mark(p, stream);
   span(p, 2, e0, e1);
   span(p, 0, e1, e2);
   span(p, 1, e2, e3);
   span(p, 2, e3, e4);
   if (p->timing) ++p->nsearch;
+  return SPS_OK;
+}
+
+extern "C" {
+
+int sps_search(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand) {
+  if (!p || !d_series || !d_ncand || (!d_cands && p->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+  const int32_t seg_len = auto_detect_seg(p);
+  const int32_t nseg = (p->nsamp + seg_len - 1) / seg_len;
+  if (nseg > 1 && (int64_t)p->ndm * p->nw * nseg > p->frag_cap) return fail(SPS_ERR_INVALID_ARG);
+  {
+    const int rc = check_domain(p, d_series, (int64_t)p->ndm * p->nsamp, stream);
+    if (rc != SPS_OK) return fail(rc);
+  }
+  const int rc = enqueue_search(p, d_series, stream, d_cands, d_ncand, p->d_med, p->d_mad, p->d_frag, seg_len);
+  if (rc != SPS_OK) return fail(rc);
+  if (finish(p, stream) != SPS_OK) return fail(SPS_ERR_HIP);
   return ok();
 }
 
@@ -501,7 +542,7 @@ int sps_search_plain(sps_plan* p, const float* d_series, hipStream_t stream, sps
   const size_t need = al(bytes_r) + al(bytes_p) + al(bytes_s) + al(bytes_f) + al(bytes_frag);
   if (p->plain_bytes < need) {
     if (p->d_plain) {
-      (void)hipDeviceSynchronize();
+      if (p->pending) (void)hipEventSynchronize(p->done);
       (void)hipFree(p->d_plain);
       p->d_plain = nullptr;
       p->plain_bytes = 0;
@@ -542,6 +583,7 @@ int sps_search_plain(sps_plan* p, const float* d_series, hipStream_t stream, sps
     if (sps::launch_plain_width(a, stream) != hipSuccess) return fail(SPS_ERR_HIP);
   }
   span(p, 3, e0, mark(p, stream));
+  if (finish(p, stream) != SPS_OK) return fail(SPS_ERR_HIP);
   return ok();
 }
 
@@ -577,6 +619,8 @@ struct sps_stream {
     uint64_t last_use;
   } graphs[kGraphCache];
   uint64_t graph_clock;
+  hipEvent_t done;      // end of the last push or flush (destroy waits for it)
+  bool pending;
 };
 
 namespace {
@@ -660,7 +704,18 @@ void stream_free(sps_stream* s) {
     for (int i = 0; i < 2; ++i)
       if (e.exec[i]) (void)hipGraphExecDestroy(e.exec[i]);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  if (s->done) (void)hipEventDestroy(s->done);
   delete s;
+}
+
+// Marks the end of a push or flush on `st`.
+int stream_finish(sps_stream* s, hipStream_t st) {
+  if (hipEventRecord(s->done, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return SPS_ERR_HIP;
+  }
+  s->pending = true;
+  return SPS_OK;
 }
 
 // Zero the carried state and put the stream start at the first sample of
@@ -704,6 +759,7 @@ int sps_stream_create(sps_plan* p, sps_stream** out) {
           hipMalloc(&s->med[i], (size_t)p->ndm * s->nbv * sizeof(int32_t)) == hipSuccess &&
           hipMalloc(&s->mad[i], (size_t)p->ndm * s->nbv * sizeof(int32_t)) == hipSuccess;
   }
+  okm = okm && hipEventCreateWithFlags(&s->done, hipEventDisableTiming) == hipSuccess;
   okm = okm && hipMalloc(&s->carry, (size_t)p->ndm * p->nw * sizeof(sps::RunSum)) == hipSuccess &&
         hipMalloc(&s->frag, (size_t)p->ndm * p->nw * s->nseg * sizeof(sps::RunSum)) == hipSuccess &&
         hipMalloc(&s->tmin, sizeof(int32_t)) == hipSuccess;
@@ -722,7 +778,8 @@ int sps_stream_create(sps_plan* p, sps_stream** out) {
 
 void sps_stream_destroy(sps_stream* s) {
   if (!s) return;
-  (void)hipDeviceSynchronize();
+  // only this stream's own pushes use its buffers: wait for the last one, not the device
+  if (s->pending) (void)hipEventSynchronize(s->done);
   stream_free(s);
 }
 
@@ -824,6 +881,7 @@ int sps_stream_push(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_
   }
   const int rc = stream_enqueue(s, d_gulp, stream, d_cands, d_ncand, s->cur, true);
   if (rc != SPS_OK) return fail(rc);
+  if (stream_finish(s, stream) != SPS_OK) return fail(SPS_ERR_HIP);
   if (gulp_offset) *gulp_offset = s->pushed;
   s->pushed += s->plan->nsamp;
   s->cur ^= 1;
@@ -886,6 +944,7 @@ int sps_stream_push_graph(sps_stream* s, const float* d_gulp, hipStream_t stream
   }
   hit->last_use = ++s->graph_clock;
   if (hipGraphLaunch(hit->exec[s->cur], stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  if (stream_finish(s, stream) != SPS_OK) return fail(SPS_ERR_HIP);
   if (gulp_offset) *gulp_offset = s->pushed;
   s->pushed += s->plan->nsamp;
   s->cur ^= 1;
@@ -897,6 +956,7 @@ int sps_stream_flush(sps_stream* s, hipStream_t stream, sps_cand* d_cands, uint3
   if (sps::launch_zero_u32(d_ncand, 1, stream) != hipSuccess) return fail(SPS_ERR_HIP);
   const sps::StreamArgs sa = stream_args(s, nullptr, d_cands, d_ncand);
   if (sps::launch_stream_close(sa, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  if (stream_finish(s, stream) != SPS_OK) return fail(SPS_ERR_HIP);
   if (end_offset) *end_offset = s->pushed;
   return ok();
 }
@@ -976,13 +1036,7 @@ int sps_footprint(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baselin
       (streaming && nsamp % sps::kStride != 0))
     return fail(SPS_ERR_INVALID_ARG);
   sps_plan p;
-  std::memset(&p, 0, sizeof(p));
-  p.ndm = ndm;
-  p.nsamp = (int32_t)nsamp;
-  p.max_width = max_width;
-  p.baseline_len = baseline_len;
-  p.nblocks = (int32_t)((nsamp + sps::kStride - 1) / sps::kStride);
-  for (int w = 1; w <= max_width; w <<= 1) ++p.nw;
+  plan_params(&p, ndm, nsamp, max_width, baseline_len, 1.0f);
   uint64_t total = 2ull * ndm * p.nblocks * sizeof(int32_t) + (uint64_t)frag_need(&p) * sizeof(sps::RunSum);
   if (streaming) {
     sps_stream s;

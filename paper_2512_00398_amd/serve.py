@@ -223,8 +223,14 @@ class GpuExecutor:
     """Device work of the serving loop: one plan + stream per admitted beam.
 
     gulp_source(beam, k) returns the device tensor [ndm][nsamp] of gulp k of
-    the beam. With keep=True every gulp's candidates are copied to the host
-    (global sample indices) for inspection; otherwise only counts are kept."""
+    the beam, produced on the caller's current stream. The search of a gulp
+    is ordered after that stream's work and the tensor is kept alive until
+    the search has finished with it. Nothing here waits for the device while
+    gulps are submitted: each gulp's completion is seen through its events.
+    With keep=True every gulp gets its own candidate buffer, copied to the
+    host once the gulp has completed (global sample indices kept for
+    inspection); otherwise the beam's buffers are reused in turn and only the
+    counts are kept."""
 
     def __init__(self, gulp_source: Callable[[int, int], "object"], nstreams: int = 4, cand_cap: int = 1 << 22,
                  cand_slots: int = 2, keep: bool = False):
@@ -232,12 +238,14 @@ class GpuExecutor:
         self.torch = torch
         self.src = gulp_source
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        self.copy_stream = torch.cuda.Stream()
         self.cap = int(cand_cap)
         self.slots = int(cand_slots)
         self.keep = keep
         self.beams: Dict[int, dict] = {}
-        self.waiting: List[Tuple[GulpRecord, object, object, object]] = []
+        self.waiting: List[tuple] = []
         self.kept: Dict[int, list] = collections.defaultdict(list)
+        self.intervals: List[Tuple[int, float, float]] = []  # (beam, device start, device end) per gulp
         self.ref = None
 
     def footprint(self, s: BeamSpec) -> int:
@@ -262,52 +270,84 @@ class GpuExecutor:
         self.beams[beam] = {"plan": plan, "stream": st, "bufs": bufs, "hs": self.streams[beam % len(self.streams)],
                             "n": 0, "spec": s}
 
+    def _clock(self, ev) -> float:
+        """Scheduler-clock seconds of a completed timing event."""
+        return self.t_ref - self.t0 + self.ref.elapsed_time(ev) * 1e-3
+
     def submit(self, rec: GulpRecord, s: BeamSpec) -> None:
         torch = self.torch
         b = self.beams[rec.beam]
         hs = b["hs"]
         x = self.src(rec.beam, rec.k)
-        cands, ncand = b["bufs"][b["n"] % self.slots]
+        # the gulp was written on the caller's stream: the search waits for it,
+        # and the allocator keeps its memory until hs is past the search
+        hs.wait_stream(torch.cuda.current_stream())
+        x.record_stream(hs)
+        if self.keep:
+            with torch.cuda.stream(hs):
+                cands = torch.empty((self.cap, 4), dtype=torch.int32, device="cuda")
+                ncand = torch.empty((1,), dtype=torch.int32, device="cuda")
+        else:
+            cands, ncand = b["bufs"][b["n"] % self.slots]
         b["n"] += 1
+        began = torch.cuda.Event(enable_timing=True)  # the beam's stream reached this gulp
+        began.record(hs)
         off = b["stream"].push(x, cands, ncand, stream=hs)
-        ev = torch.cuda.Event(enable_timing=True)   # search done: candidates in device memory
+        ev = torch.cuda.Event(enable_timing=True)     # search done: candidates in device memory
         ev.record(hs)
         host_n = torch.empty((1,), dtype=torch.int32, pin_memory=True)
         with torch.cuda.stream(hs):
             host_n.copy_(ncand, non_blocking=True)
-        copied = torch.cuda.Event()                  # count readable on the host
+        copied = torch.cuda.Event()                   # count readable on the host
         copied.record(hs)
-        if self.keep:
-            # wait for this gulp so its slot can be reused safely
-            copied.synchronize()
-            got = sps.cands_to_numpy(cands, ncand, self.cap)
-            self.kept[rec.beam].append((got, off))
-        self.waiting.append((rec, ev, copied, host_n))
+        self.waiting.append((rec, began, ev, copied, host_n, x, cands, ncand, off))
 
     def poll(self) -> List[GulpRecord]:
         done = []
         still = []
         for item in self.waiting:
-            rec, ev, copied, host_n = item
+            rec, began, ev, copied, host_n, x, cands, ncand, off = item
             if copied.query():
-                rec.done = self.t_ref - self.t0 + self.ref.elapsed_time(ev) * 1e-3
+                rec.done = self._clock(ev)
+                self.intervals.append((rec.beam, self._clock(began), rec.done))
                 rec.ncand = int(host_n.item()) & 0xFFFFFFFF
                 if rec.ncand > self.cap:
                     raise sps.SpsError(sps.SPS_ERR_OVERFLOW, "gulp %d of beam %d" % (rec.k, rec.beam))
+                if self.keep:
+                    # the gulp is complete; copy on a stream of its own so that
+                    # the beam's later gulps are not waited for
+                    with self.torch.cuda.stream(self.copy_stream):
+                        got = sps.cands_to_numpy(cands, ncand, self.cap)
+                    self.kept[rec.beam].append((got, off))
                 done.append(rec)
             else:
                 still.append(item)
         self.waiting = still
         return done
 
+    def device_overlap(self) -> Tuple[int, int]:
+        """Most gulps, and most distinct beams, whose device intervals (from the
+        beam's stream reaching the gulp to its search's end) share an instant."""
+        marks = sorted([(t0, 1, b) for b, t0, _ in self.intervals] + [(t1, -1, b) for b, _, t1 in self.intervals],
+                       key=lambda m: (m[0], m[1]))
+        live: collections.Counter = collections.Counter()
+        best_g = best_b = 0
+        for _, d, b in marks:
+            live[b] += d
+            if live[b] == 0:
+                del live[b]
+            best_g = max(best_g, sum(live.values()))
+            best_b = max(best_b, len(live))
+        return best_g, best_b
+
     def close(self, beam: int) -> None:
         b = self.beams.pop(beam)
         cands, ncand = b["bufs"][b["n"] % self.slots]
         end = b["stream"].flush(cands, ncand, stream=b["hs"])
-        b["hs"].synchronize()
         if self.keep:
+            b["hs"].synchronize()
             self.kept[beam].append((sps.cands_to_numpy(cands, ncand, self.cap), end))
-        b["stream"].close()
+        b["stream"].close()  # waits for this beam's own last push only
         b["plan"].close()
 
     def stop(self) -> None:

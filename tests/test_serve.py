@@ -165,6 +165,13 @@ def test_beam_in_mix_equals_alone_and_oracle():
     ex = serve.GpuExecutor(source, nstreams=3, cand_cap=1 << 18, keep=True)
     rep = serve.serve(sp, arr, ex, budget=1 << 40, compress=float("inf"))
     assert len(rep.records) == 18
+    # the gulps really were on the device together: submission never waits,
+    # and the device intervals of gulps of all three beams overlap
+    gulps, beams = ex.device_overlap()
+    print("in flight at once: %d (scheduler), %d gulps of %d beams (device)" % (rep.max_inflight, gulps, beams),
+          flush=True)
+    assert rep.max_inflight >= 3
+    assert beams >= 3
     for b in range(3):
         print("beam %d alone" % b, flush=True)
         alone_ex = serve.GpuExecutor(source, nstreams=1, cand_cap=1 << 18, keep=True)
