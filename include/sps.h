@@ -126,6 +126,15 @@ int sps_block_stats(sps_plan* plan, const float* d_series, hipStream_t stream, i
                     int32_t* d_mad);
 
 /*
+ * Per-width statistics (the SPS_ATTR_NORM = 2 scales) alone: for every row d
+ * and width w = 2^j, d_center[d * nw + j] = c_w and d_mad[d * nw + j] = MAD_w
+ * (device int32 [ndm][nw], nw = number of widths; 0 and 0 for widths longer
+ * than the row), whatever the plan's SPS_ATTR_NORM. Also overwrites the
+ * plan's block statistics. Section II-B, "Normalization".
+ */
+int sps_width_stats(sps_plan* plan, const float* d_series, hipStream_t stream, int32_t* d_center, int32_t* d_mad);
+
+/*
  * The same search as sps_search, executed as plain per-stage kernels with
  * every intermediate (medians, residuals, prefix sums, boxcar outputs,
  * per-position S/N decisions) materialised in device memory, one launch per
@@ -156,6 +165,15 @@ int sps_search_plain(sps_plan* plan, const float* d_series, hipStream_t stream, 
                                      II-B's normalisation read as one scale per trial and chunk). Every
                                      block of the row then reports and uses MAD_row. Plans and batches; a
                                      stream refuses a plan with 1 (the row is not complete in one gulp). */
+                                  /* 2 one scale per (DM row, width): for the boxcar-filtered series
+                                     T_w = {S_w(i) : 0 <= i <= nsamp - w}, c_w = lower median of T_w
+                                     and MAD_w = lower median of |S_w(i) - c_w|; then
+                                     snr = S_w(i) / (K * MAD_w) (no sqrt(w): MAD_w measures the filtered
+                                     series itself), a width with MAD_w = 0 has no above positions
+                                     (Section II-B's normalisation read as a scale per filtered series).
+                                     Block medians m_k unchanged. Plans and batches only: streams and
+                                     sps_search_plain refuse it. MAD_w above 2^31 - 1 (half the series
+                                     more than 2^31 from its median) is taken as 2^31 - 1. */
 #define SPS_ATTR_NBLOCKS 16       /* read-only: ceil(nsamp / 64) */
 #define SPS_ATTR_NWIDTHS 17       /* read-only: number of boxcar widths */
 #define SPS_ATTR_BLOCK_STRIDE 18  /* read-only: S = SPS_BLOCK_STRIDE, part of the arithmetic (never tuned) */

@@ -23,13 +23,14 @@ struct sps_plan {
   int32_t detect_seg;  // samples per detection segment, 0 = auto
   int32_t hist_bins;   // 4096 or 16384
   int32_t window;      // SPS_ATTR_WINDOW: 0 trailing, 1 centred (changes results)
-  int32_t norm;        // SPS_ATTR_NORM: 0 per-block MAD, 1 one MAD per row (changes results)
+  int32_t norm;        // SPS_ATTR_NORM: 0 per-block MAD, 1 one MAD per row, 2 one MAD per (row, width)
   int device;
   // scratch owned by the plan
   int32_t* d_med;
   int32_t* d_mad;
   sps::RunSum* d_frag;
   int64_t frag_cap;    // RunSum records allocated
+  int32_t* d_wstat;    // [2][ndm][nw] per-width medians c_w and MADs (SPS_ATTR_NORM = 2)
   // plain per-stage path scratch (allocated on first use)
   void* d_plain;
   size_t plain_bytes;
@@ -252,6 +253,8 @@ int ensure_frag(sps_plan* p) {
 
 static int launch_stats(sps_plan* p, const float* d_series, hipStream_t stream, int32_t* d_median,
                         int32_t* d_mad);
+static int launch_wstats(sps_plan* p, const float* d_series, hipStream_t stream, const int32_t* d_median,
+                         int32_t* center, int32_t* mad);
 
 extern "C" {
 
@@ -299,7 +302,8 @@ sps_plan* sps_plan_create(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t
   }
   const size_t stats_bytes = (size_t)ndm * p->nblocks * sizeof(int32_t);
   if (hipMalloc(&p->d_med, stats_bytes) != hipSuccess || hipMalloc(&p->d_mad, stats_bytes) != hipSuccess ||
-      hipMalloc(&p->d_flag, sizeof(uint32_t)) != hipSuccess) {
+      hipMalloc(&p->d_flag, sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&p->d_wstat, 2 * (size_t)ndm * p->nw * sizeof(int32_t)) != hipSuccess) {
     (void)hipGetLastError();
     sps_plan_destroy(p);
     fail(SPS_ERR_OOM);
@@ -324,6 +328,7 @@ void sps_plan_destroy(sps_plan* p) {
   if (p->d_frag) (void)hipFree(p->d_frag);
   if (p->d_plain) (void)hipFree(p->d_plain);
   if (p->d_flag) (void)hipFree(p->d_flag);
+  if (p->d_wstat) (void)hipFree(p->d_wstat);
   if (p->ev_pending) {
     for (auto& e : *p->ev_pending) {
       (void)hipEventDestroy(e.second.first);
@@ -397,7 +402,7 @@ int sps_plan_set(sps_plan* p, int attr, int64_t v) {
       p->window = (int32_t)v;
       return ok();
     case SPS_ATTR_NORM:
-      if (v != 0 && v != 1) return fail(SPS_ERR_INVALID_ARG);
+      if (v < 0 || v > 2) return fail(SPS_ERR_INVALID_ARG);
       p->norm = (int32_t)v;
       return ok();
     default:
@@ -434,6 +439,19 @@ int sps_block_stats(sps_plan* p, const float* d_series, hipStream_t stream, int3
   return ok();
 }
 
+int sps_width_stats(sps_plan* p, const float* d_series, hipStream_t stream, int32_t* d_center, int32_t* d_mad) {
+  if (!p || !d_series || !d_center || !d_mad) return fail(SPS_ERR_INVALID_ARG);
+  // block medians into the plan's scratch (the residual's baseline), then the series' statistics
+  const int32_t saved = p->norm;
+  p->norm = 0;
+  const int rc = launch_stats(p, d_series, stream, p->d_med, p->d_mad);
+  p->norm = saved;
+  if (rc != SPS_OK) return rc;
+  if (launch_wstats(p, d_series, stream, p->d_med, d_center, d_mad) != SPS_OK) return g_last_error;
+  if (finish(p, stream) != SPS_OK) return fail(SPS_ERR_HIP);
+  return ok();
+}
+
 }  // extern "C"
 
 static int launch_stats(sps_plan* p, const float* d_series, hipStream_t stream, int32_t* d_median, int32_t* d_mad) {
@@ -461,6 +479,15 @@ static int launch_stats(sps_plan* p, const float* d_series, hipStream_t stream, 
   return ok();
 }
 
+// Per-width scales (SPS_ATTR_NORM = 2): c_w and MAD_w of every (row, width)
+// from the block medians into center / mad ([ndm][nw] each).
+static int launch_wstats(sps_plan* p, const float* d_series, hipStream_t stream, const int32_t* d_median,
+                         int32_t* center, int32_t* mad) {
+  const sps::WidthStatsArgs w{d_series, p->nsamp, p->nsamp, p->nblocks, p->ndm, p->nw, d_median, center, mad};
+  if (sps::launch_width_stats(w, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  return ok();
+}
+
 // The fused search of one block: counter reset, block statistics into
 // med/mad, fused detection (segments of seg_len positions; run summaries of
 // segment edges in frag when a row has several segments), fix-up.
@@ -470,6 +497,10 @@ static int enqueue_search(sps_plan* p, const float* d_series, hipStream_t stream
   if (sps::launch_zero_u32(d_ncand, 1, stream) != hipSuccess) return SPS_ERR_HIP;
   hipEvent_t e1 = mark(p, stream);
   if (launch_stats(p, d_series, stream, med, mad) != SPS_OK) return g_last_error;
+  const bool wnorm = p->norm == 2;
+  int32_t* wc = wnorm ? p->d_wstat : nullptr;
+  int32_t* wm = wnorm ? p->d_wstat + (size_t)p->ndm * p->nw : nullptr;
+  if (wnorm && launch_wstats(p, d_series, stream, med, wc, wm) != SPS_OK) return g_last_error;
   hipEvent_t e2 = mark(p, stream);
   sps::DetectArgs d;
   d.seg_len = seg_len;
@@ -490,8 +521,10 @@ static int enqueue_search(sps_plan* p, const float* d_series, hipStream_t stream
   d.maxw = p->max_width;
   d.med = med;
   d.mad = mad;
+  d.wmad = wm;
   d.theta = (double)p->thresh;
-  for (int j = 0; j < sps::kMaxWidths; ++j) d.sqrtw[j] = j < p->nw ? p->sqrtw[j] : 0.0;
+  // a per-width scale measures the filtered series itself: no sqrt(w)
+  for (int j = 0; j < sps::kMaxWidths; ++j) d.sqrtw[j] = j < p->nw ? (wnorm ? 1.0 : p->sqrtw[j]) : 0.0;
   d.rows = p->ndm;
   d.row_offset = 0;
   d.cands = d_cands;
@@ -529,6 +562,7 @@ int sps_search(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand*
 
 int sps_search_plain(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand) {
   if (!p || !d_series || !d_ncand || (!d_cands && p->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+  if (p->norm == 2) return fail(SPS_ERR_INVALID_ARG);  // the per-stage path keeps per-block or per-row scales only
   {
     const int rc = check_domain(p, d_series, (int64_t)p->ndm * p->nsamp, stream);
     if (rc != SPS_OK) return fail(rc);
@@ -833,6 +867,7 @@ int stream_enqueue(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_c
   d.maxw = p->max_width;
   d.med = s->med[c];
   d.mad = s->mad[c];
+  d.wmad = nullptr;  // streams use the per-block scale only
   d.theta = (double)p->thresh;
   for (int j = 0; j < sps::kMaxWidths; ++j) d.sqrtw[j] = j < p->nw ? p->sqrtw[j] : 0.0;
   d.seg_base = s->seg_base;
@@ -1059,7 +1094,7 @@ struct sps_batch {
   int32_t stats_seg, detect_seg, hist_bins;
   int32_t window;      // SPS_ATTR_WINDOW for every item
   int32_t norm;        // SPS_ATTR_NORM for every item
-  int32_t* d_ms;       // medians then MADs of every item
+  int32_t* d_ms;       // medians then MADs of every item (then per-width c_w and MAD_w with SPS_ATTR_NORM = 2)
   int64_t ms_cap;      // int32 records
   sps::RunSum* d_frag;
   int64_t frag_cap;
@@ -1080,7 +1115,7 @@ struct BatchShape {
   int32_t nblocks, nw;
   int32_t stats_seg, stats_nseg, stats_head;
   int32_t detect_seg, detect_nseg;
-  int64_t ms_off, frag_off;
+  int64_t ms_off, frag_off, ws_off;
 };
 
 bool item_valid(const sps_batch_item& it) {
@@ -1096,6 +1131,15 @@ size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 hipError_t launch_row_mads(const std::vector<sps::RowMadArgs>& v, hipStream_t s) {
   for (const sps::RowMadArgs& r : v) {
     const hipError_t e = sps::launch_row_mad(r, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Per-width scales of a batch (SPS_ATTR_NORM = 2): one launch per item.
+hipError_t launch_width_stats_all(const std::vector<sps::WidthStatsArgs>& v, hipStream_t s) {
+  for (const sps::WidthStatsArgs& w : v) {
+    const hipError_t e = sps::launch_width_stats(w, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1159,7 +1203,7 @@ int sps_batch_set(sps_batch* b, int attr, int64_t v) {
       b->window = (int32_t)v;
       return ok();
     case SPS_ATTR_NORM:
-      if (v != 0 && v != 1) return fail(SPS_ERR_INVALID_ARG);
+      if (v < 0 || v > 2) return fail(SPS_ERR_INVALID_ARG);
       b->norm = (int32_t)v;
       return ok();
     default:
@@ -1227,6 +1271,8 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
     s.detect_nseg = (int32_t)((it.nsamp + dseg - 1) / dseg);
     s.ms_off = ms_need;
     ms_need += 2LL * it.ndm * s.nblocks;
+    s.ws_off = ms_need;
+    if (b->norm == 2) ms_need += 2LL * it.ndm * s.nw;
     s.frag_off = frag_need;
     if (s.detect_nseg > 1) {
       frag_need += (int64_t)it.ndm * s.nw * s.detect_nseg;
@@ -1302,6 +1348,7 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
   });
   int32_t acc = 0;
   std::vector<sps::RowMadArgs> row_mads;
+  std::vector<sps::WidthStatsArgs> width_stats;
   for (int32_t k = 0; k < n; ++k) {
     const BatchShape& s = ord[(size_t)k];
     const sps_batch_item& it = items[s.idx];
@@ -1322,6 +1369,9 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
     a.med = b->d_ms + s.ms_off;
     a.mad = b->d_ms + s.ms_off + (int64_t)it.ndm * s.nblocks;
     if (b->norm == 1) row_mads.push_back(sps::RowMadArgs{a.x, a.ld, a.N, a.nblocks, it.ndm, a.med, a.mad});
+    if (b->norm == 2)
+      width_stats.push_back(sps::WidthStatsArgs{a.x, a.ld, a.N, a.nblocks, it.ndm, s.nw, a.med, b->d_ms + s.ws_off,
+                                                b->d_ms + s.ws_off + (int64_t)it.ndm * s.nw});
     so[k] = acc;
     acc += a.nchains;
   }
@@ -1350,8 +1400,9 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
     a.maxw = it.max_width;
     a.med = b->d_ms + s.ms_off;
     a.mad = b->d_ms + s.ms_off + (int64_t)it.ndm * s.nblocks;
+    a.wmad = b->norm == 2 ? b->d_ms + s.ws_off + (int64_t)it.ndm * s.nw : nullptr;
     a.theta = (double)it.snr_thresh;
-    for (int j = 0; j < s.nw; ++j) a.sqrtw[j] = std::sqrt((double)(1 << j));
+    for (int j = 0; j < s.nw; ++j) a.sqrtw[j] = b->norm == 2 ? 1.0 : std::sqrt((double)(1 << j));
     a.seg_base = 0;
     a.seg_len = s.detect_seg;
     a.nseg = s.detect_nseg;
@@ -1387,7 +1438,7 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
   const int gd = (int)std::min<int64_t>(b->grid_detect[all13 ? 0 : 1], bd.total);
   if (sps::launch_batch_zero(reinterpret_cast<uint32_t* const*>(d + off_np), n, counters, stream) != hipSuccess ||
       sps::launch_block_stats_batch(bs, b->hist_bins, b->window == 1, gs, stream) != hipSuccess ||
-      launch_row_mads(row_mads, stream) != hipSuccess ||
+      launch_row_mads(row_mads, stream) != hipSuccess || launch_width_stats_all(width_stats, stream) != hipSuccess ||
       sps::launch_detect_batch(bd, all13 ? 13 : 0, gd, stream) != hipSuccess ||
       sps::launch_fixup_batch(bd, reinterpret_cast<const int32_t*>(d + off_fo), fo[n], stream) != hipSuccess ||
       hipEventRecord(b->done, stream) != hipSuccess) {

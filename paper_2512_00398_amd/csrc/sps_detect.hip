@@ -277,8 +277,11 @@ __device__ __forceinline__ void detect_body(const DetectArgs& A, const int task)
   const double tsq = tthr ? A.sqrtw[tj] : 1.0;
   const int tw = 1 << tj;
   const int tk0 = s0 - group_shift(tw) - (tw - (tw >> 1));  // centre of group 0, step 0
+  const int32_t* wmadr = A.wmad ? A.wmad + (int64_t)row * A.nw : nullptr;
   auto fetch_mad = [&](int c) -> int {
     if (!tthr) return 0;
+    // one scale per (row, width): positions outside the row are masked out
+    if (wmadr) return wmadr[tj];
     const int k = ((tk0 + c * kC) >> 6) + tg;
     return (k >= 0 && k < A.nblocks) ? madr[k] : 0;
   };

@@ -70,6 +70,21 @@ struct RowMadArgs {
   int32_t* mad;        // [rows][nblocks], overwritten
 };
 
+// Per-width re-normalisation: for every row and width w = 2^j the lower
+// median c_w of the boxcar-filtered series S_w(i), 0 <= i <= N - w, and the
+// lower MAD about it (residuals against med).
+struct WidthStatsArgs {
+  const float* x;
+  int64_t ld;          // row stride of x in samples
+  int32_t N;           // row length
+  int32_t nblocks;     // row stride of med
+  int32_t rows;
+  int32_t nw;          // widths 1 .. 2^(nw-1)
+  const int32_t* med;  // [rows][nblocks]
+  int32_t* center;     // [rows][nw] c_w
+  int32_t* mad;        // [rows][nw] MAD_w
+};
+
 // Incoherent dedispersion: words of LDS staging per channel span (8 KiB;
 // four spans per workgroup).
 constexpr int kDedispSpanWords = 2048;
@@ -133,6 +148,7 @@ struct DetectArgs {
   int32_t maxw;
   const int32_t* med;  // [rows][nblocks]
   const int32_t* mad;
+  const int32_t* wmad; // [rows][nw] one scale per (row, width) in place of mad (null: per-block mad)
   double theta;        // (double)(float) threshold
   double sqrtw[kMaxWidths];
   int32_t seg_base;    // first position of segment 0 (multiple of 1024)
@@ -234,6 +250,7 @@ hipError_t launch_detect(const DetectArgs& a, hipStream_t s);
 hipError_t launch_fixup(const DetectArgs& a, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 hipError_t launch_row_mad(const RowMadArgs& a, hipStream_t s);
+hipError_t launch_width_stats(const WidthStatsArgs& a, hipStream_t s);
 hipError_t launch_dedisp(const DedispArgs& a, hipStream_t s);
 hipError_t launch_zero_dm(const ZeroDmArgs& a, hipStream_t s);
 hipError_t launch_chan_mask(const ChanMaskArgs& a, hipStream_t s);

@@ -29,7 +29,7 @@ ATTR_HIST_BINS = 4
 ATTR_TIMING = 5
 ATTR_VALIDATE = 6
 ATTR_WINDOW = 7  # 0 trailing baseline window (default), 1 centred on its block
-ATTR_NORM = 8  # 0 per-block MAD scale (default), 1 one MAD per DM row
+ATTR_NORM = 8  # 0 per-block MAD scale (default), 1 one MAD per DM row, 2 one MAD per (DM row, width)
 NSTAGES = 4
 STAGES = ("block_stats", "detect", "fixup", "plain")
 ATTR_NBLOCKS = 16
@@ -50,6 +50,7 @@ EXPORTS = [
     ("sps_plan_destroy", None, [_P]),
     ("sps_search", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("sps_block_stats", ctypes.c_int, [_P, _P, _P, _P, _P]),
+    ("sps_width_stats", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("sps_search_plain", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("sps_plan_set", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64]),
     ("sps_plan_get", ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
@@ -197,6 +198,22 @@ class Plan:
         if rc:
             raise SpsError(rc, "sps_block_stats")
         return med, mad
+
+    def width_stats(self, series, center=None, mad=None, stream=None):
+        """Per-width statistics (sps_width_stats): int32 [ndm][nwidths] medians c_w and MADs of
+        the boxcar-filtered series."""
+        import torch
+        _check_series(series, self.ndm, self.nsamp)
+        nw = self.get(ATTR_NWIDTHS)
+        if center is None:
+            center = torch.empty((self.ndm, nw), dtype=torch.int32, device="cuda")
+        if mad is None:
+            mad = torch.empty((self.ndm, nw), dtype=torch.int32, device="cuda")
+        rc = load().sps_width_stats(self._h, series.data_ptr(), _stream_handle(stream), center.data_ptr(),
+                                    mad.data_ptr())
+        if rc:
+            raise SpsError(rc, "sps_width_stats")
+        return center, mad
 
     def timing_read(self):
         """Summed ms per stage since the last read, and the number of searches (waits for the events)."""
