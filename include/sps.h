@@ -53,6 +53,7 @@ extern "C" {
 #define SPS_ERR_HIP (-3)         /* a HIP runtime call failed (e.g. launch) */
 #define SPS_ERR_OVERFLOW (-4)    /* candidate count exceeded the capacity (reported by callers) */
 #define SPS_ERR_DOMAIN (-5)      /* input outside the supported domain */
+#define SPS_ERR_SCRATCH (-6)     /* block too large for sps_search_noalloc's fixed scratch */
 
 /* One candidate, 16 bytes. sample: first sample of the boxcar window, counted
  * from the first sample of the call's input (negative in streaming mode when
@@ -104,6 +105,33 @@ void sps_plan_destroy(sps_plan* plan);
  */
 int sps_search(sps_plan* plan, const float* d_series, hipStream_t stream, sps_cand* d_cands,
                uint32_t* d_ncand);
+
+/*
+ * Allocation-free search, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops and harnesses that forbid
+ * hipMalloc. The same search as a plan with default attributes created with
+ * these five parameters would run (SPS_ATTR_MAX_CANDS = max_cands), with the
+ * same results, but no plan is needed and the call never allocates or frees
+ * memory: its scratch (block medians and MADs, 8 bytes per 64-sample block per
+ * row rounded up to 256 bytes per array, then run summaries of detection
+ * segments) lives in a fixed device array of SPS_NOALLOC_SCRATCH_BYTES that
+ * every GPU holds, once loaded, until the process ends. Blocks whose medians
+ * and MADs do not fit (ndm * ceil(nsamp/64) > 2^23, e.g. more than 512 rows
+ * of 2^20 samples) are refused with SPS_ERR_SCRATCH and nothing is
+ * enqueued; when only the run summaries would not fit, each row is detected
+ * in one segment. All calls on one GPU share that GPU's array and the array
+ * keeps the last call's contents, so calls that overlap on one GPU (on
+ * different streams or host threads) race: order them on one stream. The
+ * first call on each device looks up the array's address (host-synchronous
+ * set-up); later calls are asynchronous on `stream` like sps_search.
+ * d_series, d_cands (capacity max_cands records, in [0, 2^32 - 1]) and
+ * d_ncand as for sps_search. Returns SPS_OK, SPS_ERR_INVALID_ARG (bad shape,
+ * parameters or pointers), SPS_ERR_SCRATCH or SPS_ERR_HIP.
+ */
+#define SPS_NOALLOC_SCRATCH_BYTES (64u << 20)
+int sps_search_noalloc(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baseline_len, float snr_thresh,
+                       const float* d_series, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand,
+                       int64_t max_cands);
 
 /*
  * Input domain (every search entry point): each sample integer-valued with

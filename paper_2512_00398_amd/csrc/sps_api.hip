@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -268,6 +269,7 @@ const char* sps_error_string(int code) {
     case SPS_ERR_HIP: return "HIP runtime error";
     case SPS_ERR_OVERFLOW: return "candidate buffer overflow";
     case SPS_ERR_DOMAIN: return "input outside the supported domain";
+    case SPS_ERR_SCRATCH: return "block larger than the allocation-free search's fixed scratch";
     default: return "unknown error";
   }
 }
@@ -557,6 +559,96 @@ int sps_search(sps_plan* p, const float* d_series, hipStream_t stream, sps_cand*
   const int rc = enqueue_search(p, d_series, stream, d_cands, d_ncand, p->d_med, p->d_mad, p->d_frag, seg_len);
   if (rc != SPS_OK) return fail(rc);
   if (finish(p, stream) != SPS_OK) return fail(SPS_ERR_HIP);
+  return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free search. Its scratch (block medians and MADs, run summaries
+// of detection-segment edges) is one file-scope device array: every GPU the
+// library runs on holds its own copy until the process ends, every call on a
+// GPU shares that GPU's copy, and the array keeps the last call's contents.
+// Host code never uses the array's name as an address: the device address is
+// looked up once per device and kept in noalloc_ptr.
+
+static __device__ __align__(256) unsigned char scratch[SPS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex noalloc_mu;
+void* noalloc_ptr[kMaxDevices];
+
+// Device address of the current device's scratch (looked up on the first call per device).
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return SPS_ERR_HIP;
+  }
+  if (dev < 0 || dev >= kMaxDevices) return SPS_ERR_HIP;
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return SPS_ERR_HIP;
+    }
+    noalloc_ptr[dev] = ptr;
+  }
+  *out = noalloc_ptr[dev];
+  return SPS_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Layout of a search's scratch in the fixed array: medians, MADs, then run
+// summaries. Detection segments follow the plan's rule, or cover whole rows
+// (no summaries) when the summaries would not fit. false: too large.
+bool noalloc_layout(const sps_plan* p, int32_t* seg_len, size_t* off_mad, size_t* off_frag) {
+  const size_t stats = align256((size_t)p->ndm * p->nblocks * sizeof(int32_t));
+  *off_mad = stats;
+  *off_frag = 2 * stats;
+  if (2 * stats > (size_t)SPS_NOALLOC_SCRATCH_BYTES) return false;
+  int32_t seg = auto_detect_seg(p);
+  const int64_t nseg = (p->nsamp + seg - 1) / seg;
+  const size_t frag = nseg > 1 ? (size_t)p->ndm * p->nw * nseg * sizeof(sps::RunSum) : 0;
+  if (2 * stats + frag > (size_t)SPS_NOALLOC_SCRATCH_BYTES)
+    seg = (int32_t)(((int64_t)p->nsamp + kDetectStep - 1) / kDetectStep * kDetectStep);  // one segment per row
+  *seg_len = seg;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sps_search_noalloc(int32_t ndm, int64_t nsamp, int32_t max_width, int32_t baseline_len, float snr_thresh,
+                       const float* d_series, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand,
+                       int64_t max_cands) {
+  if (!plan_shape_ok(ndm, nsamp, max_width, baseline_len, snr_thresh) || !d_series || !d_ncand || max_cands < 0 ||
+      max_cands > (int64_t)UINT32_MAX || (!d_cands && max_cands > 0))
+    return fail(SPS_ERR_INVALID_ARG);
+  sps_plan p;  // parameters only: no device memory, no events
+  plan_params(&p, ndm, nsamp, max_width, baseline_len, snr_thresh);
+  p.max_cands = max_cands;
+  int32_t seg_len = 0;
+  size_t off_mad = 0, off_frag = 0;
+  if (!noalloc_layout(&p, &seg_len, &off_mad, &off_frag)) return fail(SPS_ERR_SCRATCH);
+  void* base = nullptr;
+  {
+    const int rc = noalloc_scratch(&base);
+    if (rc != SPS_OK) return fail(rc);
+  }
+  // nothing in the scratch needs to start at zero: the statistics kernel writes
+  // every block's median and MAD, and the detection kernel every run summary,
+  // before anything reads them
+  char* b = static_cast<char*>(base);
+  const int rc = enqueue_search(&p, d_series, stream, d_cands, d_ncand, reinterpret_cast<int32_t*>(b),
+                                reinterpret_cast<int32_t*>(b + off_mad), reinterpret_cast<sps::RunSum*>(b + off_frag),
+                                seg_len);
+  if (rc != SPS_OK) return fail(rc);
   return ok();
 }
 

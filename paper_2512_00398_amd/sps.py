@@ -21,6 +21,8 @@ SPS_ERR_OOM = -2
 SPS_ERR_HIP = -3
 SPS_ERR_OVERFLOW = -4
 SPS_ERR_DOMAIN = -5
+SPS_ERR_SCRATCH = -6
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 ATTR_MAX_CANDS = 1
 ATTR_STATS_SEG = 2
@@ -49,6 +51,8 @@ EXPORTS = [
     ("sps_plan_create", _P, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float]),
     ("sps_plan_destroy", None, [_P]),
     ("sps_search", ctypes.c_int, [_P, _P, _P, _P, _P]),
+    ("sps_search_noalloc", ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_float, _P, _P, _P, _P, ctypes.c_int64]),
     ("sps_block_stats", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("sps_width_stats", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("sps_search_plain", ctypes.c_int, [_P, _P, _P, _P, _P]),
@@ -412,6 +416,20 @@ def search(series, max_width: int, baseline_len: int, snr_thresh: float, capacit
         p.search(series, cands, ncand, plain=plain)
         torch.cuda.synchronize()
         return cands_to_numpy(cands, ncand, p.max_cands)
+
+
+def search_noalloc(series, max_width: int, baseline_len: int, snr_thresh: float, cands, ncand, stream=None):
+    """The search without a plan and without allocating device memory
+    (sps_search_noalloc): scratch from the library's fixed per-GPU array.
+    cands is an int32 [capacity][4] GPU tensor, ncand an int32 [1] GPU tensor."""
+    ndm, nsamp = series.shape
+    _check_series(series, ndm, nsamp)
+    rc = load().sps_search_noalloc(int(ndm), int(nsamp), int(max_width), int(baseline_len), float(snr_thresh),
+                                   series.data_ptr(), _stream_handle(stream), cands.data_ptr(), ncand.data_ptr(),
+                                   int(cands.shape[0]))
+    if rc:
+        raise SpsError(rc, "sps_search_noalloc")
+    return cands, ncand
 
 
 class Clusterer:
