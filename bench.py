@@ -25,6 +25,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # 32-bit integer vector adds: 256 CUs x 64 lanes per clock x 2.4 GHz
 ALU_INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# the dedispersion kernel adds packed pairs of 16-bit sums: one 32-bit add
+# retires two sample additions, so its attainable rate is twice the int32 rate
+ALU_PAIR_ADD_PEAK_TOPS = 2 * ALU_INT32_PEAK_TOPS
 
 # HBM bytes per launch on the default workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a
@@ -46,6 +49,20 @@ MEASURED_TRAFFIC = {
     "block_stats": ("2e9d5d2d1e7f0a73", (4349788 * 2 + 137113) * 1024),
     "dedisp": ("a0a762ea61972dd1", (3436542 * 2 + 1048576) * 1024),
 }
+
+
+# VALU wave-instructions per launch on the default workload, from rocprofv3
+# SQ_INSTS_VALU (profiles/); reported only while the sources are unchanged.
+VALU_ISSUE_PER_S = 256 * 2.4e9
+MEASURED_VALU = {
+}
+
+
+def measured_issue(kernel: str):
+    ent = MEASURED_VALU.get(kernel)
+    if not ent or ent[0] != sources_hash(kernel):
+        return None
+    return ent[1]
 
 
 def sources_hash(kernel: str) -> str:
@@ -70,31 +87,47 @@ def log(*a):
 
 def _oracle_row(args):
     """CPU-baseline worker: the oracle on one row of the workload (timed inside)."""
-    cfg_index, row, centred, row_norm = args
+    cfg_index, row, centred, row_norm, width_norm = args
     import numpy as np  # noqa: F401
     import oracle
     import synth
     b = synth.config(cfg_index)["blocks"][0]
     x = synth.generate(b, rows=[row], nthreads=1)
     t0 = time.time()
-    c = oracle.search(x, b.max_width, b.baseline_len, b.snr_thresh, centered=centred, row_norm=row_norm)
+    c = oracle.search(x, b.max_width, b.baseline_len, b.snr_thresh, centered=centred, row_norm=row_norm,
+                      width_norm=width_norm)
     t1 = time.time()
     return t0, t1, int(c.size), b.nsamp
 
 
-def cpu_baseline(cfg_index: int, nrows: int, centred: bool = False, row_norm: bool = False):
-    procs = max(1, min(16, os.cpu_count() or 1, nrows))
+def host_cores() -> int:
+    """Cores this process may run on (the affinity mask, not the machine's count)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(cfg_index: int, nrows: int, centred: bool = False, row_norm: bool = False,
+                 width_norm: bool = False):
+    """The oracle on a bounded sample of whole DM rows, one process per core
+    (at most 16, the host share of one GPU), timed as wall clock over the
+    sample; the rate is samples of the sampled rows per second."""
+    cores = host_cores()
+    procs = max(1, min(16, cores, nrows))
     ndm = __import__("synth").config(cfg_index)["blocks"][0].ndm
     rows = [int(r * (ndm - 1) / max(1, nrows - 1)) for r in range(nrows)]
     ctx = mp.get_context("spawn")
     with ctx.Pool(procs) as pool:
-        res = pool.map(_oracle_row, [(cfg_index, r, centred, row_norm) for r in rows])
+        res = pool.map(_oracle_row, [(cfg_index, r, centred, row_norm, width_norm) for r in rows])
     span = max(r[1] for r in res) - min(r[0] for r in res)
     samples = sum(r[3] for r in res)
-    return {"value": samples / span, "unit": "DM-trial-samples/s", "cores": procs, "kind": "oracle",
-            "sample": "%d of %d DM rows (full 2^%d-sample rows), one process per row" %
-                      (nrows, ndm, (res[0][3]).bit_length() - 1),
-            "seconds": round(span, 3)}
+    return {"value": samples / span, "unit": "DM-trial-samples/s", "cores": procs, "host_cores": cores,
+            "kind": "oracle",
+            "sample": "%d of %d DM rows (whole 2^%d-sample rows), numpy oracle, one process per row on %d of the "
+                      "%d host cores; rate over the sampled rows (the full block scales linearly in rows)" %
+                      (nrows, ndm, (res[0][3]).bit_length() - 1, procs, cores),
+            "cpu_seconds": round(sum(r[1] - r[0] for r in res), 2), "seconds": round(span, 3)}
 
 
 def bench_stream(args):
@@ -268,7 +301,7 @@ def bench_dedisp(args):
     k.close()
     adds = float(ndm) * nchan * nout
     achieved = adds / (kms * 1e-3) / 1e12
-    peak = ALU_INT32_PEAK_TOPS
+    peak = ALU_PAIR_ADD_PEAK_TOPS
     print(json.dumps({
         "metric": "DM-trial-samples/s", "value": ndm * nout / (ms * 1e-3), "unit": "DM-trial-samples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -276,6 +309,8 @@ def bench_dedisp(args):
         "config": {"workload": "dedisp: 1024 channels 1050-1450 MHz, tsamp 49.152 us, 1024 trial DMs 0-1000, "
                                "%d output samples (%d input)" % (nout, nin)},
         "roofline": {"bound": "alu", "kernel": "dedisp", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+                     "peak_note": "sample additions per second: 32-bit adds of packed 16-bit pairs (2 per lane per "
+                                  "clock, 256 CUs x 64 lanes x 2.4 GHz)",
                      "frac": achieved / peak, "traffic": measured_traffic("dedisp"),
                      "algorithmic_ops": adds, "algorithmic_bytes": float(nchan) * nin + 4.0 * ndm * nout},
         "kernel_ms": kms,
@@ -447,8 +482,9 @@ def main():
                     help="tune the plan's speed-only attributes on the input first (untimed; cached as JSON)")
     ap.add_argument("--window", default="trailing", choices=["trailing", "centred"],
                     help="baseline window placement (SPS_ATTR_WINDOW)")
-    ap.add_argument("--norm", default="block", choices=["block", "row"],
-                    help="noise scale: per-block MAD or one MAD per DM row (SPS_ATTR_NORM)")
+    ap.add_argument("--norm", default="block", choices=["block", "row", "width"],
+                    help="noise scale: per-block MAD, one MAD per DM row, or one MAD per (DM row, width) "
+                         "(SPS_ATTR_NORM 0, 1, 2)")
     ap.add_argument("--mode", default="search", choices=["search", "copy"],
                     help="copy: time a plain device-to-device copy of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -485,7 +521,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on %d rows" % args.cpu_rows)
-        cpu = cpu_baseline(args.config, args.cpu_rows, args.window == "centred", args.norm == "row")
+        cpu = cpu_baseline(args.config, args.cpu_rows, args.window == "centred", args.norm == "row",
+                           args.norm == "width")
         log("cpu baseline: %.3g samples/s on %d cores" % (cpu["value"], cpu["cores"]))
 
     import numpy as np
@@ -501,7 +538,7 @@ def main():
     del x
     stream = torch.cuda.current_stream()
     plan = sps.Plan(b.ndm, b.nsamp, b.max_width, b.baseline_len, b.snr_thresh)
-    variant = {sps.ATTR_WINDOW: int(args.window == "centred"), sps.ATTR_NORM: int(args.norm == "row")}
+    variant = {sps.ATTR_WINDOW: int(args.window == "centred"), sps.ATTR_NORM: {"block": 0, "row": 1, "width": 2}[args.norm]}
     for attr, v in variant.items():
         plan.set(attr, v)
     default_variant = not any(variant.values())
@@ -529,6 +566,8 @@ def main():
 
     # the plain per-stage path on the same input (comparison only, not the metric)
     plain_ms = None
+    if args.norm == "width":
+        args.no_plain = True  # the per-stage path keeps per-block or per-row scales only
     if not args.no_plain:
         plan.search(xd, cands, ncand, stream=stream, plain=True)
         torch.cuda.synchronize()
@@ -587,16 +626,19 @@ def main():
     samples = b.ndm * b.nsamp
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = samples * args.steps / (t1 - t0)
-    nblocks = plan.nblocks
     avg = {k: v / max(1, nsearch) for k, v in stages.items()}
-    # algorithmic bytes per launch of each kernel
-    bytes_stats = b.ndm * (4.0 * b.nsamp + 8.0 * nblocks)
-    if args.norm == "row":
-        bytes_stats += b.ndm * 8.0 * b.nsamp  # the row scale's two passes over the row
-    bytes_detect = b.ndm * (4.0 * b.nsamp + 8.0 * nblocks) + 16.0 * n
+    # Algorithmic bytes: 4 B per DM-trial-sample (the FP32 block read once)
+    # plus 16 B per candidate written; the medians and MADs that pass from the
+    # statistics kernel to the detection kernel are not algorithmic traffic.
+    alg_bytes = 4.0 * samples + 16.0 * n
     dom = "block_stats" if avg["block_stats"] >= avg["detect"] else "detect"
-    dom_bytes = bytes_stats if dom == "block_stats" else bytes_detect
+    dom_bytes = 4.0 * samples + (16.0 * n if dom == "detect" else 0.0)
     achieved = dom_bytes / (avg[dom] * 1e-3) / 1e9
+    issue = measured_issue(dom) if args.config == 2 and default_variant else None
+    if issue:
+        issue = {"valu_wave_instructions_per_launch": issue, "valu_issue_ms": issue / VALU_ISSUE_PER_S * 1e3,
+                 "valu_issue_frac_of_kernel_time": issue / VALU_ISSUE_PER_S / (avg[dom] * 1e-3),
+                 "peak_note": "one VALU wave-instruction per CU per clock: 256 CUs x 2.4 GHz"}
     out = {
         "metric": "DM-trial-samples/s",
         "value": value,
@@ -617,8 +659,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom) if args.config == 2 and default_variant else None,
-                     "algorithmic_bytes": dom_bytes},
-        "path_hbm_frac": 4.0 * value / 1e9 / HBM_PEAK_GBS,
+                     "algorithmic_bytes": dom_bytes, "issue": issue},
+        "path_roofline": {"achieved": alg_bytes / (ms_per_step * 1e-3) / 1e9, "unit": "GB/s",
+                          "frac": alg_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "algorithmic_bytes": alg_bytes, "note": "whole search (every kernel) per step"},
         "stages_ms": {k: round(v, 4) for k, v in avg.items() if k != "plain"},
         "plain_ms_per_step": plain_ms,
         "fused_vs_plain": (plain_ms / ms_per_step) if plain_ms else None,

@@ -1,4 +1,7 @@
 """Comparison helpers for GPU-vs-oracle parity (test support, no GPU code)."""
+import multiprocessing as mp
+import os
+
 import numpy as np
 
 SNR_RTOL = 1e-4        # per-candidate S/N tolerance
@@ -43,3 +46,26 @@ def exact_equal(a, b):
     return (np.array_equal(a["sample"].astype(np.int64), b["sample"].astype(np.int64))
             and np.array_equal(a["dm_idx"], b["dm_idx"]) and np.array_equal(a["width"], b["width"])
             and np.array_equal(a["snr"].view(np.uint32), b["snr"].view(np.uint32)))
+
+
+def _oracle_row(args):
+    x_row, row_id, max_width, L, theta, kw = args
+    import oracle
+    return oracle.search(x_row[None, :], max_width, L, theta, row_ids=[row_id], with_stats=True, **kw)
+
+
+def oracle_rows(x, rows, max_width, L, theta, **kw):
+    """oracle.search(x, ..., rows=rows, with_stats=True, **kw), one process per
+    row (at most 16): returns candidates sorted (dm, width, sample) and the
+    stacked block medians and MADs of the rows, in the order given."""
+    import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    procs = max(1, min(16, cores, len(rows)))
+    tasks = [(np.ascontiguousarray(x[r]), int(r), max_width, L, theta, kw) for r in rows]
+    with mp.get_context("spawn").Pool(procs) as pool:
+        res = pool.map(_oracle_row, tasks)
+    cands = oracle.sort_cands(np.concatenate([c for c, _, _ in res]))
+    return cands, np.concatenate([m for _, m, _ in res]), np.concatenate([d for _, _, d in res])
