@@ -306,6 +306,26 @@ typedef struct {
 
 typedef struct sps_batch sps_batch;
 int sps_batch_create(sps_batch** out);
+/*
+ * sps_batch_push: continuous batching of streams (the serving loop's gulps
+ *   of many beams, Section IV-C's overlapped chunk processing): one gulp of
+ *   each of n distinct streams (streams[i], device FP32 d_gulps[i] of its
+ *   plan's shape) searched by one persistent launch per stage over all of
+ *   them, then each stream's carry folded and rolled forward. Results,
+ *   carried state and *gulp_offsets (host int64[n], may be NULL) are exactly
+ *   those of calling sps_stream_push(streams[i], d_gulps[i], stream,
+ *   d_cands[i], d_ncand[i], &gulp_offsets[i]) for each i; streams may have
+ *   different shapes and parameters. d_cands / d_ncand are host arrays of n
+ *   device pointers (capacity: the stream's plan SPS_ATTR_MAX_CANDS). A
+ *   stream may appear once per call (its next gulp needs this one's carry);
+ *   it must not be used concurrently elsewhere. Uses the context's
+ *   SPS_ATTR_HIST_BINS; plan timing is not recorded. Asynchronous, except
+ *   that a call needing larger tables than any earlier one first waits for
+ *   the context's earlier work. SPS_OK, SPS_ERR_INVALID_ARG (nothing
+ *   enqueued), SPS_ERR_DOMAIN (plan validation), SPS_ERR_OOM, SPS_ERR_HIP.
+ */
+int sps_batch_push(sps_batch* b, sps_stream* const* streams, const float* const* d_gulps, int32_t n,
+                   hipStream_t stream, sps_cand* const* d_cands, uint32_t* const* d_ncand, int64_t* gulp_offsets);
 int sps_batch_set(sps_batch* b, int attr, int64_t value);
 int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipStream_t stream);
 void sps_batch_destroy(sps_batch* b);

@@ -10,6 +10,12 @@ and an order-independent 64-bit digest of the records), and it raises if not.
 Results are kept in a JSON file keyed by GPU architecture and shape class
 (ndm and nsamp rounded up to powers of two, max_width, baseline_len). The file
 is SPS_AUTOTUNE_CACHE if set, else ~/.cache/sps/autotune.json.
+
+A batch of blocks (sps_batch_search) is tuned the same way as a whole: the
+same three attributes apply to every item, every configuration must return
+every item's candidate set unchanged, and the result is cached under the
+multiset of the items' shape classes. The fused kernels evaluate every width
+in one pass over the samples, so there is no widths-per-pass attribute.
 """
 from __future__ import annotations
 
@@ -175,4 +181,99 @@ def apply(plan: sps.Plan, path: Optional[str] = None, arch: Optional[str] = None
     cfg = lookup(plan.ndm, plan.nsamp, plan.max_width, plan.baseline_len, arch or gpu_arch(), path)
     if cfg:
         _apply(plan, cfg)
+    return cfg
+
+
+def batch_key(arch: str, shapes) -> str:
+    """Cache key of a batch: the sorted multiset of its items' shape classes.
+    shapes: (ndm, nsamp, max_width, baseline_len) per item."""
+    classes = {}
+    for ndm, nsamp, w, L in shapes:
+        k = shape_key(arch, ndm, nsamp, w, L).split("|", 1)[1]
+        classes[k] = classes.get(k, 0) + 1
+    return "%s|batch|%s" % (arch, ";".join("%dx%s" % (classes[k], k) for k in sorted(classes)))
+
+
+def batch_candidate_configs(shapes) -> Dict[str, List[int]]:
+    """Values tried for a batch: chain lengths and detection segments that fit its items."""
+    nb_max = max((n + sps.BLOCK_STRIDE - 1) // sps.BLOCK_STRIDE for _, n, _, _ in shapes)
+    min_chain = max(max(64, (4 * L + 63) // 64) for _, _, _, L in shapes)
+    stats = [0] + [s for s in (256, 512, 1024, 2048, 4096, 8192) if min_chain // 2 <= s < nb_max]
+    wmax = max(w for _, _, w, _ in shapes)
+    nmax = max(n for _, n, _, _ in shapes)
+    detect = [0] + [s for s in (16384, 32768, 65536, 131072, 262144) if s >= 4 * wmax and s < nmax]
+    return {"stats_seg": stats, "detect_seg": detect, "hist_bins": [4096, 16384]}
+
+
+def _batch_apply(batch: sps.Batch, cfg: dict) -> None:
+    for k, v in cfg.items():
+        batch.set(ATTRS[k], int(v))
+
+
+def _batch_measure(batch: sps.Batch, items, stream, steps: int):
+    import torch
+    batch.search(items, stream=stream)
+    torch.cuda.synchronize()
+    res = []
+    for (x, w, L, th, cands, ncand) in items:
+        n = int(ncand.item()) & 0xFFFFFFFF
+        if n > cands.shape[0]:
+            raise sps.SpsError(sps.SPS_ERR_OVERFLOW, "autotune batch")
+        res.append((n, digest(cands[:n].cpu().numpy())))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        batch.search(items, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, tuple(res)
+
+
+def tune_batch(batch: sps.Batch, items, stream=None, steps: int = 2, path: Optional[str] = None,
+               arch: Optional[str] = None, log=None) -> dict:
+    """Coordinate search over the batch's tuning attributes on `items` (the
+    sps.Batch.search item tuples); records and applies the best. Every
+    configuration must return each item's candidates unchanged."""
+    import torch
+    stream = torch.cuda.current_stream() if stream is None else stream
+    arch = arch or gpu_arch()
+    shapes = [(int(x.shape[0]), int(x.shape[1]), int(w), int(L)) for (x, w, L, _, _, _) in items]
+    key = batch_key(arch, shapes)
+    best = dict(DEFAULT)
+    _batch_apply(batch, best)
+    best_ms, ref = _batch_measure(batch, items, stream, steps)
+    default_ms = best_ms
+    tried = 1
+    for attr, values in batch_candidate_configs(shapes).items():
+        for v in values:
+            if v == best[attr]:
+                continue
+            cfg = dict(best)
+            cfg[attr] = v
+            _batch_apply(batch, cfg)
+            ms, res = _batch_measure(batch, items, stream, steps)
+            tried += 1
+            if res != ref:
+                raise RuntimeError("tuning %s changed a batch result" % cfg)
+            if log:
+                log("autotune batch %s: %.3f ms" % (cfg, ms))
+            if ms < best_ms:
+                best_ms, best = ms, cfg
+    _batch_apply(batch, best)
+    data = load_cache(path)
+    data[key] = {"config": best, "ms": best_ms, "default_ms": default_ms, "tried": tried,
+                 "when": time.strftime("%Y-%m-%dT%H:%M:%S")}
+    save_cache(data, path)
+    return {"key": key, "config": best, "ms": best_ms, "default_ms": default_ms, "tried": tried}
+
+
+def apply_batch(batch: sps.Batch, shapes, path: Optional[str] = None, arch: Optional[str] = None) -> Optional[dict]:
+    """Set the cached configuration for this batch's multiset of shape classes, if any; returns it."""
+    ent = load_cache(path).get(batch_key(arch or gpu_arch(), shapes))
+    if not ent:
+        return None
+    cfg = ent.get("config", {})
+    if set(cfg) - set(ATTRS):
+        raise ValueError("autotune cache entry has unknown attributes: %s" % sorted(cfg))
+    _batch_apply(batch, cfg)
     return cfg

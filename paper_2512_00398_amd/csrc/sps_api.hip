@@ -913,20 +913,10 @@ void sps_stream_destroy(sps_stream* s) {
 
 namespace {
 
-// Enqueue one gulp step reading history buffer `c` (no host state changes;
-// capturable: kernels only). `timed`: record tracing events.
-int stream_enqueue(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand,
-                   int c, bool timed) {
-  sps_plan* p = s->plan;
-  struct TimingGuard {  // tracing events are not recorded into captured graphs
-    sps_plan* p;
-    int saved;
-    ~TimingGuard() { p->timing = saved; }
-  } guard{p, p->timing};
-  if (!timed) p->timing = 0;
-  hipEvent_t e0 = mark(p, stream);
-  if (sps::launch_zero_u32(d_ncand, 1, stream) != hipSuccess) return SPS_ERR_HIP;
-  hipEvent_t e1 = mark(p, stream);
+// Statistics of one gulp of stream s reading history buffer c: only the
+// gulp's blocks, windows reaching back into the history.
+sps::StatsArgs stream_stats_args(const sps_stream* s, const float* d_gulp, int c) {
+  const sps_plan* p = s->plan;
   sps::StatsArgs a;
   a.x = d_gulp;
   a.ld = p->nsamp;
@@ -945,8 +935,14 @@ int stream_enqueue(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_c
   a.tmin = s->tmin;
   a.med = s->med[c];
   a.mad = s->mad[c];
-  if (sps::launch_block_stats(a, p->hist_bins, stream) != hipSuccess) return SPS_ERR_HIP;
-  hipEvent_t e2 = mark(p, stream);
+  return a;
+}
+
+// Detection of one gulp of stream s reading history buffer c: window ends
+// inside the gulp; runs at segment edges are left to k_stream_fold.
+sps::DetectArgs stream_detect_args(const sps_stream* s, const float* d_gulp, sps_cand* d_cands, uint32_t* d_ncand,
+                                   int c) {
+  const sps_plan* p = s->plan;
   sps::DetectArgs d;
   d.x = d_gulp;
   d.ld = p->nsamp;
@@ -975,6 +971,27 @@ int stream_enqueue(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_c
   d.ncand = d_ncand;
   d.cap = (uint32_t)p->max_cands;
   d.frag = s->frag;
+  return d;
+}
+
+// Enqueue one gulp step reading history buffer `c` (no host state changes;
+// capturable: kernels only). `timed`: record tracing events.
+int stream_enqueue(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand,
+                   int c, bool timed) {
+  sps_plan* p = s->plan;
+  struct TimingGuard {  // tracing events are not recorded into captured graphs
+    sps_plan* p;
+    int saved;
+    ~TimingGuard() { p->timing = saved; }
+  } guard{p, p->timing};
+  if (!timed) p->timing = 0;
+  hipEvent_t e0 = mark(p, stream);
+  if (sps::launch_zero_u32(d_ncand, 1, stream) != hipSuccess) return SPS_ERR_HIP;
+  hipEvent_t e1 = mark(p, stream);
+  const sps::StatsArgs a = stream_stats_args(s, d_gulp, c);
+  if (sps::launch_block_stats(a, p->hist_bins, stream) != hipSuccess) return SPS_ERR_HIP;
+  hipEvent_t e2 = mark(p, stream);
+  const sps::DetectArgs d = stream_detect_args(s, d_gulp, d_cands, d_ncand, c);
   if (sps::launch_detect(d, stream) != hipSuccess) return SPS_ERR_HIP;
   hipEvent_t e3 = mark(p, stream);
   sps::StreamArgs sa = stream_args(s, d_gulp, d_cands, d_ncand);
@@ -1252,6 +1269,44 @@ int grow(T** p, int64_t* cap, int64_t need) {
   return SPS_OK;
 }
 
+// Workspace of a batch call: grows the scratch and the item tables (waiting
+// for the context's earlier work first), queries the resident grids, orders
+// `stream` after the previous call and waits until the pinned staging of the
+// tables may be rewritten.
+int batch_prepare(sps_batch* b, size_t tab_bytes, int64_t ms_need, int64_t frag_need, bool all13,
+                  hipStream_t stream) {
+  if (ms_need > b->ms_cap || frag_need > b->frag_cap || tab_bytes > b->tab_cap) {
+    if (b->pending && hipEventSynchronize(b->done) != hipSuccess) return SPS_ERR_HIP;
+    if (ms_need > 0 && grow(&b->d_ms, &b->ms_cap, ms_need) != SPS_OK) return SPS_ERR_OOM;
+    if (frag_need > 0 && grow(&b->d_frag, &b->frag_cap, frag_need) != SPS_OK) return SPS_ERR_OOM;
+    if (tab_bytes > b->tab_cap) {
+      if (b->d_tab) (void)hipFree(b->d_tab);
+      if (b->h_tab) (void)hipHostFree(b->h_tab);
+      b->d_tab = nullptr;
+      b->h_tab = nullptr;
+      b->tab_cap = 0;
+      const size_t cap = std::max<size_t>(tab_bytes, 64 * 1024);
+      if (hipMalloc(reinterpret_cast<void**>(&b->d_tab), cap) != hipSuccess ||
+          hipHostMalloc(reinterpret_cast<void**>(&b->h_tab), cap, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return SPS_ERR_OOM;
+      }
+      b->tab_cap = cap;
+    }
+  }
+  const int bins = b->hist_bins == 16384 ? 1 : 0;
+  if (!b->grid_stats[bins]) b->grid_stats[bins] = sps::block_stats_batch_grid(b->hist_bins);
+  if (!b->grid_detect[all13 ? 0 : 1]) b->grid_detect[all13 ? 0 : 1] = sps::detect_batch_grid(all13 ? 13 : 0);
+  if (b->grid_stats[bins] <= 0 || b->grid_detect[all13 ? 0 : 1] <= 0) return SPS_ERR_HIP;
+  // order after the previous call (possibly on another stream), and wait
+  // until the staging buffer is free again
+  if (b->pending) {
+    if (hipStreamWaitEvent(stream, b->done, 0) != hipSuccess) return SPS_ERR_HIP;
+    if (hipEventSynchronize(b->uploaded) != hipSuccess) return SPS_ERR_HIP;
+  }
+  return SPS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1390,37 +1445,11 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
   const size_t off_ct = align16(off_np + (size_t)n * sizeof(uint32_t*));
   const size_t tab_bytes = align16(off_ct + 2 * sizeof(uint32_t));
 
-  // Workspace: growing waits for the context's earlier work.
-  if (ms_need > b->ms_cap || frag_need > b->frag_cap || tab_bytes > b->tab_cap) {
-    if (b->pending && hipEventSynchronize(b->done) != hipSuccess) return fail(SPS_ERR_HIP);
-    if (grow(&b->d_ms, &b->ms_cap, ms_need) != SPS_OK) return fail(SPS_ERR_OOM);
-    if (frag_need > 0 && grow(&b->d_frag, &b->frag_cap, frag_need) != SPS_OK) return fail(SPS_ERR_OOM);
-    if (tab_bytes > b->tab_cap) {
-      if (b->d_tab) (void)hipFree(b->d_tab);
-      if (b->h_tab) (void)hipHostFree(b->h_tab);
-      b->d_tab = nullptr;
-      b->h_tab = nullptr;
-      b->tab_cap = 0;
-      const size_t cap = std::max<size_t>(tab_bytes, 64 * 1024);
-      if (hipMalloc(reinterpret_cast<void**>(&b->d_tab), cap) != hipSuccess ||
-          hipHostMalloc(reinterpret_cast<void**>(&b->h_tab), cap, hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(SPS_ERR_OOM);
-      }
-      b->tab_cap = cap;
-    }
+  {
+    const int rc = batch_prepare(b, tab_bytes, ms_need, frag_need, all13, stream);
+    if (rc != SPS_OK) return fail(rc);
   }
   const int bins = b->hist_bins == 16384 ? 1 : 0;
-  if (!b->grid_stats[bins]) b->grid_stats[bins] = sps::block_stats_batch_grid(b->hist_bins);
-  if (!b->grid_detect[all13 ? 0 : 1]) b->grid_detect[all13 ? 0 : 1] = sps::detect_batch_grid(all13 ? 13 : 0);
-  if (b->grid_stats[bins] <= 0 || b->grid_detect[all13 ? 0 : 1] <= 0) return fail(SPS_ERR_HIP);
-
-  // Order after the previous call (possibly on another stream), and wait
-  // until the staging buffer is free again.
-  if (b->pending) {
-    if (hipStreamWaitEvent(stream, b->done, 0) != hipSuccess) return fail(SPS_ERR_HIP);
-    if (hipEventSynchronize(b->uploaded) != hipSuccess) return fail(SPS_ERR_HIP);
-  }
 
   char* h = b->h_tab;
   char* d = b->d_tab;
@@ -1529,15 +1558,118 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
   const int gs = (int)std::min<int64_t>(b->grid_stats[bins], (bs.total + wpg - 1) / wpg);
   const int gd = (int)std::min<int64_t>(b->grid_detect[all13 ? 0 : 1], bd.total);
   if (sps::launch_batch_zero(reinterpret_cast<uint32_t* const*>(d + off_np), n, counters, stream) != hipSuccess ||
-      sps::launch_block_stats_batch(bs, b->hist_bins, b->window == 1, gs, stream) != hipSuccess ||
+      sps::launch_block_stats_batch(bs, b->hist_bins, b->window == 1, false, gs, stream) != hipSuccess ||
       launch_row_mads(row_mads, stream) != hipSuccess || launch_width_stats_all(width_stats, stream) != hipSuccess ||
-      sps::launch_detect_batch(bd, all13 ? 13 : 0, gd, stream) != hipSuccess ||
+      sps::launch_detect_batch(bd, all13 ? 13 : 0, false, gd, stream) != hipSuccess ||
       sps::launch_fixup_batch(bd, reinterpret_cast<const int32_t*>(d + off_fo), fo[n], stream) != hipSuccess ||
       hipEventRecord(b->done, stream) != hipSuccess) {
     b->pending = true;
     return fail(SPS_ERR_HIP);
   }
   b->pending = true;
+  return ok();
+}
+
+int sps_batch_push(sps_batch* b, sps_stream* const* streams, const float* const* d_gulps, int32_t n,
+                   hipStream_t stream, sps_cand* const* d_cands, uint32_t* const* d_ncand, int64_t* gulp_offsets) {
+  if (!b || n < 0 || (n > 0 && (!streams || !d_gulps || !d_cands || !d_ncand))) return fail(SPS_ERR_INVALID_ARG);
+  if (n == 0) return ok();
+  bool all13 = true;
+  for (int32_t i = 0; i < n; ++i) {
+    const sps_stream* s = streams[i];
+    if (!s || !d_gulps[i] || !d_ncand[i] || (!d_cands[i] && s->plan->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+    for (int32_t k = 0; k < i; ++k)
+      if (streams[k] == s) return fail(SPS_ERR_INVALID_ARG);  // one gulp per stream: the next needs this one's carry
+    all13 = all13 && s->plan->nw == sps::kMaxWidths;
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    const int rc = check_domain(streams[i]->plan, d_gulps[i], (int64_t)streams[i]->plan->ndm * streams[i]->plan->nsamp,
+                                stream);
+    if (rc != SPS_OK) return fail(rc);
+  }
+  // Tables: statistics and detection arguments of every gulp, task offsets,
+  // counter pointers, queue heads.
+  const size_t off_sa = 0;
+  const size_t off_da = align16(off_sa + (size_t)n * sizeof(sps::StatsArgs));
+  const size_t off_so = align16(off_da + (size_t)n * sizeof(sps::DetectArgs));
+  const size_t off_do = align16(off_so + (size_t)(n + 1) * sizeof(int32_t));
+  const size_t off_np = align16(off_do + (size_t)(n + 1) * sizeof(int32_t));
+  const size_t off_ct = align16(off_np + (size_t)n * sizeof(uint32_t*));
+  const size_t tab_bytes = align16(off_ct + 2 * sizeof(uint32_t));
+  {
+    const int rc = batch_prepare(b, tab_bytes, 0, 0, all13, stream);
+    if (rc != SPS_OK) return fail(rc);
+  }
+  const int bins = b->hist_bins == 16384 ? 1 : 0;
+  char* h = b->h_tab;
+  char* d = b->d_tab;
+  auto* sa = reinterpret_cast<sps::StatsArgs*>(h + off_sa);
+  auto* da = reinterpret_cast<sps::DetectArgs*>(h + off_da);
+  auto* so = reinterpret_cast<int32_t*>(h + off_so);
+  auto* dof = reinterpret_cast<int32_t*>(h + off_do);
+  auto* np = reinterpret_cast<uint32_t**>(h + off_np);
+  // queues ordered by task cost, largest first (chains: window + segment;
+  // detection segments: segment + widest halo)
+  std::vector<int32_t> ord((size_t)n);
+  for (int32_t i = 0; i < n; ++i) ord[(size_t)i] = i;
+  std::vector<sps::StatsArgs> st((size_t)n);
+  std::vector<sps::DetectArgs> dt((size_t)n);
+  for (int32_t i = 0; i < n; ++i) {
+    st[(size_t)i] = stream_stats_args(streams[i], d_gulps[i], streams[i]->cur);
+    dt[(size_t)i] = stream_detect_args(streams[i], d_gulps[i], d_cands[i], d_ncand[i], streams[i]->cur);
+  }
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+    return st[(size_t)x].seg_blocks + st[(size_t)x].L / 64 > st[(size_t)y].seg_blocks + st[(size_t)y].L / 64;
+  });
+  int32_t acc = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    sa[k] = st[(size_t)ord[(size_t)k]];
+    so[k] = acc;
+    acc += sa[k].nchains;
+  }
+  so[n] = acc;
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+    return dt[(size_t)x].seg_len + dt[(size_t)x].maxw > dt[(size_t)y].seg_len + dt[(size_t)y].maxw;
+  });
+  acc = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    da[k] = dt[(size_t)ord[(size_t)k]];
+    dof[k] = acc;
+    acc += da[k].rows * da[k].nseg;
+  }
+  dof[n] = acc;
+  for (int32_t i = 0; i < n; ++i) np[i] = d_ncand[i];
+  if (hipMemcpyAsync(d, h, tab_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipEventRecord(b->uploaded, stream) != hipSuccess) return fail(SPS_ERR_HIP);
+  uint32_t* counters = reinterpret_cast<uint32_t*>(d + off_ct);
+  sps::BatchStats bs{reinterpret_cast<const sps::StatsArgs*>(d + off_sa), reinterpret_cast<const int32_t*>(d + off_so),
+                     n, so[n], counters};
+  sps::BatchDetect bd{reinterpret_cast<const sps::DetectArgs*>(d + off_da),
+                      reinterpret_cast<const int32_t*>(d + off_do), n, dof[n], counters + 1};
+  const int wpg = b->hist_bins == 16384 ? 2 : 4;
+  const int gs = (int)std::min<int64_t>(b->grid_stats[bins], (bs.total + wpg - 1) / wpg);
+  const int gd = (int)std::min<int64_t>(b->grid_detect[all13 ? 0 : 1], bd.total);
+  bool okl = sps::launch_batch_zero(reinterpret_cast<uint32_t* const*>(d + off_np), n, counters, stream) == hipSuccess &&
+             sps::launch_block_stats_batch(bs, b->hist_bins, false, true, gs, stream) == hipSuccess &&
+             sps::launch_detect_batch(bd, all13 ? 13 : 0, true, gd, stream) == hipSuccess;
+  // each stream folds its open runs and rolls its history forward
+  for (int32_t i = 0; okl && i < n; ++i) {
+    const sps::StreamArgs fa = stream_args(streams[i], d_gulps[i], d_cands[i], d_ncand[i]);
+    okl = sps::launch_stream_fold(fa, stream) == hipSuccess && sps::launch_stream_advance(fa, stream) == hipSuccess &&
+          stream_finish(streams[i], stream) == SPS_OK;
+  }
+  okl = okl && hipEventRecord(b->done, stream) == hipSuccess;
+  b->pending = true;
+  if (!okl) {
+    (void)hipGetLastError();
+    return fail(SPS_ERR_HIP);
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    sps_stream* s = streams[i];
+    if (gulp_offsets) gulp_offsets[i] = s->pushed;
+    s->pushed += s->plan->nsamp;
+    s->cur ^= 1;
+  }
   return ok();
 }
 

@@ -647,7 +647,7 @@ __global__ __launch_bounds__(256) void k_detect(DetectArgs A) {
 // Four waves per SIMD (at most 128 VGPRs): reading each item's arguments from
 // memory costs registers, and the kernel is faster at this occupancy even
 // with the two spilled registers it takes.
-template <int NW>
+template <int NW, bool VIRT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_detect_batch(BatchDetect B) {
   __shared__ int s_task;
   while (true) {
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (task >= B.total) break;
     int it = 0;
     while (it + 1 < B.nitems && B.offs[it + 1] <= task) ++it;
-    detect_body<NW, false>(B.items[it], task - B.offs[it]);
+    detect_body<NW, VIRT>(B.items[it], task - B.offs[it]);
     __syncthreads();
   }
 }
@@ -822,10 +822,15 @@ hipError_t launch_stream_advance(const StreamArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_detect_batch(const BatchDetect& b, int nw_all, int grid, hipStream_t s) {
+hipError_t launch_detect_batch(const BatchDetect& b, int nw_all, bool virt, int grid, hipStream_t s) {
   if (b.total <= 0) return hipSuccess;
-  if (nw_all == 13) hipLaunchKernelGGL((k_detect_batch<13>), dim3(grid), dim3(256), 0, s, b);
-  else hipLaunchKernelGGL((k_detect_batch<0>), dim3(grid), dim3(256), 0, s, b);
+  if (virt) {
+    if (nw_all == 13) hipLaunchKernelGGL((k_detect_batch<13, true>), dim3(grid), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_detect_batch<0, true>), dim3(grid), dim3(256), 0, s, b);
+  } else {
+    if (nw_all == 13) hipLaunchKernelGGL((k_detect_batch<13, false>), dim3(grid), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_detect_batch<0, false>), dim3(grid), dim3(256), 0, s, b);
+  }
   return hipGetLastError();
 }
 
@@ -833,8 +838,9 @@ int detect_batch_grid(int nw_all) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  hipError_t e = nw_all == 13 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_detect_batch<13>, 256, 0)
-                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_detect_batch<0>, 256, 0);
+  hipError_t e = nw_all == 13
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_detect_batch<13, false>, 256, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_detect_batch<0, false>, 256, 0);
   if (e != hipSuccess) return 0;
   return cus * (per > 0 ? per : 1);
 }

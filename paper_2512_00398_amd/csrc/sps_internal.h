@@ -258,9 +258,9 @@ hipError_t launch_validate(const float* x, int64_t n, float bound, uint32_t* bad
 hipError_t launch_stream_fold(const StreamArgs& a, hipStream_t s);
 hipError_t launch_stream_advance(const StreamArgs& a, hipStream_t s);
 hipError_t launch_stream_close(const StreamArgs& a, hipStream_t s);
-hipError_t launch_block_stats_batch(const BatchStats& b, int hist_bins, bool lead, int grid, hipStream_t s);
+hipError_t launch_block_stats_batch(const BatchStats& b, int hist_bins, bool lead, bool virt, int grid, hipStream_t s);
 int block_stats_batch_grid(int hist_bins);  // resident workgroups on the current device (0: error)
-hipError_t launch_detect_batch(const BatchDetect& b, int nw_all, int grid, hipStream_t s);
+hipError_t launch_detect_batch(const BatchDetect& b, int nw_all, bool virt, int grid, hipStream_t s);
 int detect_batch_grid(int nw_all);
 hipError_t launch_fixup_batch(const BatchDetect& b, const int32_t* d_offs, int total, hipStream_t s);
 hipError_t launch_batch_zero(uint32_t* const* d_ncand, int n, uint32_t* counters, hipStream_t s);

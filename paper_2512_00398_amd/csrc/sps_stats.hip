@@ -452,8 +452,9 @@ __global__ __launch_bounds__(64 * WPG) void k_block_stats(StatsArgs a) {
 }
 
 // Persistent form over a batch: every wave takes chains from the queue on its
-// own (no block barriers) until the counter passes the total.
-template <int NB, int WPG, bool LEAD>
+// own (no block barriers) until the counter passes the total. VIRT: the items
+// are gulps of streams (rows read through their histories).
+template <int NB, int WPG, bool VIRT, bool LEAD>
 __global__ __launch_bounds__(64 * WPG) void k_block_stats_batch(BatchStats B) {
   __shared__ uint32_t hist[WPG][NB / 2];
   const int wave = threadIdx.x >> 6;
@@ -465,7 +466,7 @@ __global__ __launch_bounds__(64 * WPG) void k_block_stats_batch(BatchStats B) {
     if (task >= B.total) break;
     int it = 0;
     while (it + 1 < B.nitems && B.offs[it + 1] <= task) ++it;
-    stats_chain<NB, false, LEAD>(B.items[it], task - B.offs[it], hist[wave], lane);
+    stats_chain<NB, VIRT, LEAD>(B.items[it], task - B.offs[it], hist[wave], lane);
   }
 }
 
@@ -490,14 +491,19 @@ hipError_t launch_block_stats(const StatsArgs& a, int hist_bins, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_block_stats_batch(const BatchStats& b, int hist_bins, bool lead, int grid, hipStream_t s) {
+hipError_t launch_block_stats_batch(const BatchStats& b, int hist_bins, bool lead, bool virt, int grid, hipStream_t s) {
   if (b.total <= 0) return hipSuccess;
+  if (virt && lead) return hipErrorInvalidValue;  // streams use the trailing window only
   if (hist_bins == 16384) {
-    if (lead) hipLaunchKernelGGL((k_block_stats_batch<16384, 2, true>), dim3(grid), dim3(128), 0, s, b);
-    else hipLaunchKernelGGL((k_block_stats_batch<16384, 2, false>), dim3(grid), dim3(128), 0, s, b);
+    const dim3 g(grid), t(128);
+    if (virt) hipLaunchKernelGGL((k_block_stats_batch<16384, 2, true, false>), g, t, 0, s, b);
+    else if (lead) hipLaunchKernelGGL((k_block_stats_batch<16384, 2, false, true>), g, t, 0, s, b);
+    else hipLaunchKernelGGL((k_block_stats_batch<16384, 2, false, false>), g, t, 0, s, b);
   } else {
-    if (lead) hipLaunchKernelGGL((k_block_stats_batch<4096, 4, true>), dim3(grid), dim3(256), 0, s, b);
-    else hipLaunchKernelGGL((k_block_stats_batch<4096, 4, false>), dim3(grid), dim3(256), 0, s, b);
+    const dim3 g(grid), t(256);
+    if (virt) hipLaunchKernelGGL((k_block_stats_batch<4096, 4, true, false>), g, t, 0, s, b);
+    else if (lead) hipLaunchKernelGGL((k_block_stats_batch<4096, 4, false, true>), g, t, 0, s, b);
+    else hipLaunchKernelGGL((k_block_stats_batch<4096, 4, false, false>), g, t, 0, s, b);
   }
   return hipGetLastError();
 }
@@ -508,8 +514,8 @@ int block_stats_batch_grid(int hist_bins) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   // resident workgroups are limited by LDS, the same for both window placements
   hipError_t e = hist_bins == 16384
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_block_stats_batch<16384, 2, false>, 128, 0)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_block_stats_batch<4096, 4, false>, 256, 0);
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_block_stats_batch<16384, 2, false, false>, 128, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_block_stats_batch<4096, 4, false, false>, 256, 0);
   if (e != hipSuccess) return 0;
   return cus * (per > 0 ? per : 1);
 }

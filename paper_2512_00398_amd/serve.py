@@ -12,11 +12,11 @@ The scheduler is plain host logic and runs against any executor:
   input and candidate buffers) fits in what is left of the memory budget;
   otherwise it waits, first come first served, until admitted beams finish.
 - Dispatch: every arriving gulp of an admitted beam is enqueued as soon as
-  one of `slots` in-flight places is free (continuous: no batch is formed or
-  waited for; arrivals beyond the slots wait first come first served). A
-  beam's gulps stay in order on the device stream the beam is bound to; beams
-  are spread over a few device streams so that gulps of different beams
-  overlap on the GPU.
+  one of `slots` in-flight places is free (continuous: nothing waits for a
+  batch to fill; arrivals beyond the slots wait first come first served).
+  Gulps that become ready together are handed over together: a batching
+  executor searches gulps of different beams in one launch per stage while
+  earlier launches are still on the device. A beam's gulps stay in order.
 - Latency of a gulp: from its arrival to the completion of its search on the
   device (candidates in device memory).
 
@@ -168,16 +168,26 @@ def serve(specs: Sequence[BeamSpec], arrivals: Sequence[Arrival], executor, budg
     def due(a: Arrival) -> float:
         return 0.0 if compress == float("inf") else a.t / compress
 
-    def submit(a: Arrival, arrived: float) -> None:
-        rec = GulpRecord(a.beam, a.k, arrived, now())
-        executor.submit(rec, specs[a.beam])
-        inflight[id(rec)] = rec
-        state["samples"] += specs[a.beam].ndm * specs[a.beam].nsamp
-        state["max_inflight"] = max(state["max_inflight"], len(inflight))
+    many = getattr(executor, "submit_many", None)
 
     def dispatch() -> None:
+        # every ready gulp that has a slot goes to the device now; an executor
+        # that batches takes them together (gulps of different beams share a launch)
+        group = []
         while ready and (slots is None or len(inflight) < slots):
-            submit(*ready.popleft())
+            a, arrived = ready.popleft()
+            rec = GulpRecord(a.beam, a.k, arrived, now())
+            inflight[id(rec)] = rec
+            state["samples"] += specs[a.beam].ndm * specs[a.beam].nsamp
+            group.append((rec, specs[a.beam]))
+        if not group:
+            return
+        if many is not None:
+            many(group)
+        else:
+            for rec, spec in group:
+                executor.submit(rec, spec)
+        state["max_inflight"] = max(state["max_inflight"], len(inflight))
 
     def admit(beams: List[int]) -> None:
         for b in beams:
@@ -233,12 +243,22 @@ class GpuExecutor:
     counts are kept."""
 
     def __init__(self, gulp_source: Callable[[int, int], "object"], nstreams: int = 4, cand_cap: int = 1 << 22,
-                 cand_slots: int = 2, keep: bool = False):
+                 cand_slots: int = 2, keep: bool = False, batch: bool = False):
         import torch
         self.torch = torch
         self.src = gulp_source
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
         self.copy_stream = torch.cuda.Stream()
+        # batch=True: gulps submitted together go through one persistent launch
+        # per stage (sps_batch_push), one round per set of distinct beams; the
+        # rounds rotate over the device streams (a context per stream), and a
+        # beam's gulp waits for the event of its previous gulp when that ran on
+        # another stream. Otherwise each beam pushes on its own device stream.
+        self.batches = [sps.Batch() for _ in self.streams] if batch else None
+        self.batch = self.batches
+        self.round = 0
+        self.last_event: Dict[int, Tuple[object, object]] = {}  # beam -> (device stream, event of its last gulp)
+        self.batch_sizes: List[int] = []
         self.cap = int(cand_cap)
         self.slots = int(cand_slots)
         self.keep = keep
@@ -274,10 +294,11 @@ class GpuExecutor:
         """Scheduler-clock seconds of a completed timing event."""
         return self.t_ref - self.t0 + self.ref.elapsed_time(ev) * 1e-3
 
-    def submit(self, rec: GulpRecord, s: BeamSpec) -> None:
+    def _prepare(self, rec: GulpRecord, hs=None):
+        """The gulp's tensor, ordered on device stream hs (default: the beam's), and its candidate buffers."""
         torch = self.torch
         b = self.beams[rec.beam]
-        hs = b["hs"]
+        hs = b["hs"] if hs is None else hs
         x = self.src(rec.beam, rec.k)
         # the gulp was written on the caller's stream: the search waits for it,
         # and the allocator keeps its memory until hs is past the search
@@ -290,17 +311,66 @@ class GpuExecutor:
         else:
             cands, ncand = b["bufs"][b["n"] % self.slots]
         b["n"] += 1
+        return b, hs, x, cands, ncand
+
+    def _track(self, hs, recs, began, ev, xs, cands, ncands, offs) -> None:
+        """Count copies and completion events of gulps just enqueued on hs."""
+        torch = self.torch
+        for rec, x, c, n, off in zip(recs, xs, cands, ncands, offs):
+            host_n = torch.empty((1,), dtype=torch.int32, pin_memory=True)
+            with torch.cuda.stream(hs):
+                host_n.copy_(n, non_blocking=True)
+            copied = torch.cuda.Event()               # count readable on the host
+            copied.record(hs)
+            self.waiting.append((rec, began, ev, copied, host_n, x, c, n, off))
+
+    def submit(self, rec: GulpRecord, s: BeamSpec) -> None:
+        if self.batch is not None:
+            return self.submit_many([(rec, s)])
+        torch = self.torch
+        b, hs, x, cands, ncand = self._prepare(rec)
         began = torch.cuda.Event(enable_timing=True)  # the beam's stream reached this gulp
         began.record(hs)
         off = b["stream"].push(x, cands, ncand, stream=hs)
         ev = torch.cuda.Event(enable_timing=True)     # search done: candidates in device memory
         ev.record(hs)
-        host_n = torch.empty((1,), dtype=torch.int32, pin_memory=True)
-        with torch.cuda.stream(hs):
-            host_n.copy_(ncand, non_blocking=True)
-        copied = torch.cuda.Event()                   # count readable on the host
-        copied.record(hs)
-        self.waiting.append((rec, began, ev, copied, host_n, x, cands, ncand, off))
+        self._track(hs, [rec], began, ev, [x], [cands], [ncand], [off])
+
+    def submit_many(self, group) -> None:
+        """Gulps (rec, spec) that became ready together. With batching, each
+        round of distinct beams is one sps_batch_push; a beam's next gulp goes
+        to the next round (it needs this one's carry)."""
+        if self.batch is None:
+            for rec, s in group:
+                self.submit(rec, s)
+            return
+        torch = self.torch
+        pending = list(group)
+        while pending:
+            seen, now_, later = set(), [], []
+            for rec, s in pending:
+                (later if rec.beam in seen else now_).append((rec, s))
+                seen.add(rec.beam)
+            pending = later
+            k = self.round % len(self.streams)
+            self.round += 1
+            hs = self.streams[k]
+            for rec, _ in now_:
+                prev = self.last_event.get(rec.beam)
+                if prev is not None and prev[0] is not hs:
+                    hs.wait_event(prev[1])  # the beam's previous gulp (and its carry) first
+            prep = [self._prepare(rec, hs) for rec, _ in now_]
+            began = torch.cuda.Event(enable_timing=True)
+            began.record(hs)
+            offs = self.batches[k].push([p[0]["stream"] for p in prep], [p[2] for p in prep], [p[3] for p in prep],
+                                        [p[4] for p in prep], stream=hs)
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(hs)
+            for rec, _ in now_:
+                self.last_event[rec.beam] = (hs, ev)
+            self.batch_sizes.append(len(now_))
+            self._track(hs, [rec for rec, _ in now_], began, ev, [p[2] for p in prep], [p[3] for p in prep],
+                        [p[4] for p in prep], offs)
 
     def poll(self) -> List[GulpRecord]:
         done = []
@@ -343,6 +413,9 @@ class GpuExecutor:
     def close(self, beam: int) -> None:
         b = self.beams.pop(beam)
         cands, ncand = b["bufs"][b["n"] % self.slots]
+        prev = self.last_event.pop(beam, None)
+        if prev is not None and prev[0] is not b["hs"]:
+            b["hs"].wait_event(prev[1])
         end = b["stream"].flush(cands, ncand, stream=b["hs"])
         if self.keep:
             b["hs"].synchronize()
@@ -352,3 +425,6 @@ class GpuExecutor:
 
     def stop(self) -> None:
         self.torch.cuda.synchronize()
+        if self.batches is not None:
+            for bt in self.batches:
+                bt.close()

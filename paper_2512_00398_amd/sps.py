@@ -73,6 +73,7 @@ EXPORTS = [
     ("sps_batch_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p)]),
     ("sps_batch_set", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64]),
     ("sps_batch_search", ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
+    ("sps_batch_push", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     ("sps_batch_destroy", None, [_P]),
     ("sps_cluster_create", _P, [ctypes.c_uint32]),
     ("sps_cluster_run", ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
@@ -370,6 +371,27 @@ class Batch:
         rc = load().sps_batch_search(self._h, ctypes.cast(arr, ctypes.c_void_p), len(items), _stream_handle(stream))
         if rc:
             raise SpsError(rc, "sps_batch_search")
+
+    def push(self, streams, gulps, cands, ncands, stream=None):
+        """One gulp of each of several distinct Streams in one persistent launch
+        per stage (sps_batch_push); returns each gulp's global first-sample index.
+        gulps: float32 GPU tensors of each stream's gulp shape; cands / ncands:
+        each stream's candidate buffers (int32 [capacity][4], int32 [1])."""
+        n = len(streams)
+        if not (len(gulps) == len(cands) == len(ncands) == n):
+            raise ValueError("one gulp and one candidate buffer pair per stream")
+        for st, g in zip(streams, gulps):
+            _check_series(g, st.plan.ndm, st.plan.nsamp)
+        P = ctypes.c_void_p * max(1, n)
+        hs = P(*[st._h for st in streams])
+        gs = P(*[g.data_ptr() for g in gulps])
+        cs = P(*[c.data_ptr() for c in cands])
+        ns = P(*[c.data_ptr() for c in ncands])
+        offs = (ctypes.c_int64 * max(1, n))()
+        rc = load().sps_batch_push(self._h, hs, gs, n, _stream_handle(stream), cs, ns, offs)
+        if rc:
+            raise SpsError(rc, "sps_batch_push")
+        return [int(offs[i]) for i in range(n)]
 
     def close(self) -> None:
         if getattr(self, "_h", None):

@@ -75,3 +75,53 @@ def test_tuned_plan_gives_oracle_result(tmp_path):
     g = np.empty(got.size, dtype=oracle.CAND_DTYPE)
     g["sample"], g["dm_idx"], g["width"], g["snr"] = got["sample"], got["dm_idx"], got["width"], got["snr"]
     assert exact_equal(oracle.sort_cands(g), ref)
+
+
+def test_batch_key_is_a_multiset_of_shape_classes():
+    a = autotune.batch_key("gfx950", [(256, 1 << 16, 4096, 16384), (1000, 1 << 20, 4096, 16384),
+                                      (256, 60000, 4096, 16384)])
+    b = autotune.batch_key("gfx950", [(1024, 1 << 20, 4096, 16384), (256, 65536, 4096, 16384),
+                                      (200, 65000, 4096, 16384)])
+    assert a == b == "gfx950|batch|1xndm1024|n1048576|w4096|L16384;2xndm256|n65536|w4096|L16384"
+    assert a != autotune.batch_key("gfx950", [(256, 1 << 16, 4096, 16384), (1000, 1 << 20, 4096, 16384)])
+
+
+def test_batch_candidate_configs_fit_the_items():
+    shapes = [(256, 1 << 16, 4096, 16384), (2048, 1 << 20, 4096, 16384)]
+    c = autotune.batch_candidate_configs(shapes)
+    assert c["stats_seg"][0] == 0 and c["detect_seg"][0] == 0
+    assert all(s >= 4 * 4096 and s < (1 << 20) for s in c["detect_seg"][1:])
+    assert all(s < (1 << 20) // 64 for s in c["stats_seg"][1:])
+    assert sorted(c["hist_bins"]) == [4096, 16384]
+
+
+@pytest.mark.gpu
+def test_tuned_batch_keeps_every_item_result(tmp_path):
+    import torch
+    import oracle
+    import synth
+    from paper_2512_00398_amd import sps
+    shapes = [(4, 30000, 1024, 3000, 6.0), (9, 9000, 256, 16384, 5.0), (2, 70000, 4096, 4096, 6.0)]
+    blocks = [synth.Block(ndm=nd, nsamp=n, max_width=w, baseline_len=L, snr_thresh=th, seed=330 + k, n_pulses=4,
+                          pulse_width=(1, 256), pulse_snr=(6.0, 25.0)) for k, (nd, n, w, L, th) in enumerate(shapes)]
+    xs = [synth.generate(b) for b in blocks]
+    items = []
+    for b, x in zip(blocks, xs):
+        cands = torch.empty((1 << 20, 4), dtype=torch.int32, device="cuda")
+        ncand = torch.zeros((1,), dtype=torch.int32, device="cuda")
+        items.append((torch.from_numpy(x).cuda(), b.max_width, b.baseline_len, b.snr_thresh, cands, ncand))
+    path = str(tmp_path / "tune.json")
+    print("tune batch of %d items" % len(items), flush=True)
+    with sps.Batch() as bt:
+        res = autotune.tune_batch(bt, items, steps=1, path=path)  # raises if any configuration changes a result
+        assert res["tried"] > 1 and res["ms"] <= res["default_ms"]
+        bt.search(items)
+        torch.cuda.synchronize()
+        for (x, w, L, th, c, n), xh in zip(items, xs):
+            got = sps.cands_to_numpy(c, n)
+            ref = oracle.search(xh, w, L, th)
+            assert got.size == ref.size and np.array_equal(got["sample"].astype(np.int64), ref["sample"])
+    with sps.Batch() as bt2:
+        cfg = autotune.apply_batch(bt2, [(int(x.shape[0]), int(x.shape[1]), w, L) for (x, w, L, _, _, _) in items],
+                                   path=path)
+        assert cfg == res["config"]

@@ -217,3 +217,54 @@ def test_stream_validation_rejects_bad_gulp():
         assert st.push(torch.from_numpy(x).cuda(), c, n) == 1024
         torch.cuda.synchronize()
         st.close()
+
+
+def _globalise(c, off):
+    a = np.empty(c.size, dtype=oracle.CAND_DTYPE)
+    a["sample"] = c["sample"].astype(np.int64) + off
+    a["dm_idx"], a["width"], a["snr"] = c["dm_idx"], c["width"], c["snr"]
+    return a
+
+
+def test_batch_push_equals_stream_push_and_oracle():
+    # Gulps of three streams of different shapes and parameters pushed
+    # together (one persistent launch per stage per round, sps_batch_push):
+    # each stream's candidates and offsets equal its own pushes and the oracle
+    # on its concatenated observation.
+    import torch
+    m = sps()
+    shapes = [(6, 4096, 512, 3000, 5.0, 3), (3, 8192, 4096, 5000, 5.5, 3), (9, 2048, 64, 700, 4.5, 3)]
+    blocks = [synth.Block(ndm=nd, nsamp=g * ng, max_width=w, baseline_len=L, snr_thresh=th, seed=810 + k, n_pulses=6,
+                          pulse_width=(1, min(w, 256)), pulse_snr=(6.0, 25.0), straddle_period=g)
+              for k, (nd, g, w, L, th, ng) in enumerate(shapes)]
+    xs = [synth.generate(b) for b in blocks]
+    plans = [m.Plan(nd, g, w, L, th) for (nd, g, w, L, th, _) in shapes]
+    streams = [m.Stream(p) for p in plans]
+    bufs = [p.alloc_cands() for p in plans]
+    parts = [[] for _ in shapes]
+    print("batch push of %d streams" % len(shapes), flush=True)
+    with m.Batch() as b:
+        with pytest.raises(m.SpsError):  # one gulp per stream and call
+            g0 = torch.from_numpy(np.ascontiguousarray(xs[0][:, :shapes[0][1]])).cuda()
+            b.push([streams[0], streams[0]], [g0, g0], [bufs[0][0]] * 2, [bufs[0][1]] * 2)
+        for k in range(3):
+            gulps = [torch.from_numpy(np.ascontiguousarray(x[:, k * s[1]:(k + 1) * s[1]])).cuda()
+                     for x, s in zip(xs, shapes)]
+            offs = b.push(streams, gulps, [c for c, _ in bufs], [n for _, n in bufs])
+            torch.cuda.synchronize()
+            assert offs == [k * s[1] for s in shapes]
+            for i, (c, n) in enumerate(bufs):
+                parts[i].append(_globalise(m.cands_to_numpy(c, n, plans[i].max_cands), offs[i]))
+    for i, (st, (c, n)) in enumerate(zip(streams, bufs)):
+        end = st.flush(c, n)
+        torch.cuda.synchronize()
+        parts[i].append(_globalise(m.cands_to_numpy(c, n, plans[i].max_cands), end))
+        got = oracle.sort_cands(np.concatenate(parts[i]))
+        nd, g, w, L, th, ng = shapes[i]
+        alone = run_stream(xs[i], g, w, L, th)
+        assert exact_equal(got, alone), i
+        ref = oracle.search(xs[i], w, L, th)
+        assert compare_cands(got, ref, th, "batch push %d" % i) == 0 and exact_equal(got, ref), i
+        st.close()
+    for p in plans:
+        p.close()

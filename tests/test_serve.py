@@ -194,3 +194,51 @@ def test_serve_slots_cap_inflight_and_keep_order():
     assert rep.max_inflight == 3
     for b in range(len(sp)):
         assert ex.order[b] == list(range(8))
+
+
+@pytest.mark.gpu
+def test_batched_serving_equals_alone_and_oracle():
+    # Continuous batching: gulps of four beams that are ready together go
+    # through one launch per stage (sps_batch_push); each beam's candidates
+    # equal the beam served alone (its own pushes) and the oracle.
+    import torch
+    import oracle
+    import synth
+    from parity import exact_equal
+    gulp = 4096
+    specs_ = [(6, 512, 3000, 91), (3, 4096, 5000, 92), (9, 64, 700, 93), (4, 1024, 2000, 94)]
+    blocks = [synth.Block(ndm=nd, nsamp=5 * gulp, max_width=w, baseline_len=L, seed=sd, n_pulses=6,
+                          pulse_width=(1, min(w, 256)), pulse_snr=(6.0, 25.0), straddle_period=gulp)
+              for nd, w, L, sd in specs_]
+    xs = [synth.generate(b) for b in blocks]
+    dev = [torch.from_numpy(x).cuda() for x in xs]
+    sp = [serve.BeamSpec(ndm=b.ndm, nsamp=gulp, max_width=b.max_width, baseline_len=b.baseline_len,
+                         snr_thresh=5.0) for b in blocks]
+
+    def source(beam, k):
+        return dev[beam][:, k * gulp:(k + 1) * gulp].contiguous()
+
+    def collect(kept):
+        parts = []
+        for c, off in kept:
+            a = np.empty(c.size, dtype=oracle.CAND_DTYPE)
+            a["sample"] = c["sample"].astype(np.int64) + off
+            a["dm_idx"], a["width"], a["snr"] = c["dm_idx"], c["width"], c["snr"]
+            parts.append(a)
+        return oracle.sort_cands(np.concatenate(parts))
+
+    arr = serve.poisson_arrivals(sp, 1.5, seed=19, gulps_per_beam=5)
+    print("batched serve", [(s.ndm, s.nsamp, s.max_width) for s in sp], flush=True)
+    ex = serve.GpuExecutor(source, cand_cap=1 << 18, keep=True, batch=True)
+    rep = serve.serve(sp, arr, ex, budget=1 << 40, compress=float("inf"))
+    assert len(rep.records) == 20
+    print("launch sizes", ex.batch_sizes, flush=True)
+    assert max(ex.batch_sizes) >= 3  # gulps of at least three beams shared one launch
+    for b in range(len(sp)):
+        alone_ex = serve.GpuExecutor(source, nstreams=1, cand_cap=1 << 18, keep=True)
+        serve.serve(sp, [serve.Arrival(float(k), b, k) for k in range(5)], alone_ex, budget=1 << 40,
+                    compress=float("inf"))
+        mix, alone = collect(ex.kept[b]), collect(alone_ex.kept[b])
+        assert exact_equal(mix, alone), b
+        ref = oracle.search(xs[b], blocks[b].max_width, blocks[b].baseline_len, 5.0)
+        assert exact_equal(mix, ref), b
