@@ -335,14 +335,30 @@ def bench_batch(args):
         x = synth.generate(b)
         xs.append(torch.from_numpy(x).cuda())
         del x
-        cands = torch.empty((1 << 24, 4), dtype=torch.int32, device="cuda")
+        # room for the drift flood (about 0.8% of the samples become candidates)
+        cap = min((1 << 32) - 1, int(0.012 * b.ndm * b.nsamp) + (1 << 16))
+        cands = torch.empty((cap, 4), dtype=torch.int32, device="cuda")
         ncand = torch.zeros((1,), dtype=torch.int32, device="cuda")
         outs.append((cands, ncand))
         items.append((xs[-1], b.max_width, b.baseline_len, b.snr_thresh, cands, ncand))
         plans.append(sps.Plan(b.ndm, b.nsamp, b.max_width, b.baseline_len, b.snr_thresh))
+        plans[-1].set(sps.ATTR_MAX_CANDS, cap)
     log("generated %d files, %.3g samples" % (len(blocks), sum(b.ndm * b.nsamp for b in blocks)))
     stream = torch.cuda.current_stream()
     batch = sps.Batch()
+    # the batch runs on the autotuner's configuration for its shape classes
+    # (tuned now, untimed, if the cache has none); every configuration tried
+    # must return every file's candidates unchanged
+    from paper_2512_00398_amd import autotune
+    shapes = [(b.ndm, b.nsamp, b.max_width, b.baseline_len) for b in blocks]
+    tuned = autotune.apply_batch(batch, shapes)
+    tuned_from = "cache"
+    if tuned is None:
+        res = autotune.tune_batch(batch, items, stream=stream, steps=1, log=log)
+        tuned, tuned_from = res["config"], "tuned now (default %.1f ms, tuned %.1f ms)" % (res["default_ms"], res["ms"])
+    log("batch tuning: %s (%s)" % (tuned, tuned_from))
+    for p, b in zip(plans, blocks):
+        autotune.apply(p)  # per-file plans take their own cached configuration, if any
 
     def run_batch():
         batch.search(items, stream=stream)
@@ -365,10 +381,13 @@ def bench_batch(args):
         return (time.perf_counter() - t0) * 1e3 / steps, e0.elapsed_time(e1) / steps
 
     ms_batch, dev_batch = timed(run_batch, args.steps)
-    n_batch = [int(n.item()) for _, n in outs]
+    n_batch = [int(n.item()) & 0xFFFFFFFF for _, n in outs]
+    for (c, _), nb in zip(outs, n_batch):
+        if nb > c.shape[0]:
+            raise SystemExit("candidate buffer overflow in the batch (%d > %d)" % (nb, c.shape[0]))
     log("batch: %.3f ms/step" % ms_batch)
     ms_loop, dev_loop = timed(run_loop, args.steps)
-    n_loop = [int(n.item()) for _, n in outs]
+    n_loop = [int(n.item()) & 0xFFFFFFFF for _, n in outs]
     log("per-file loop: %.3f ms/step" % ms_loop)
     if n_batch != n_loop:
         raise SystemExit("batch and per-file candidate counts differ")
@@ -386,6 +405,9 @@ def bench_batch(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "per_file_loop_ms_per_step": ms_loop,
         "batch_vs_loop": ms_loop / ms_batch,
+        "tuning": {"config": tuned, "source": tuned_from,
+                   "attributes": "chain length (blocks), detection segment (samples), histogram span; every width "
+                                 "is evaluated in one pass, so there is no widths-per-pass attribute"},
         "candidates": sum(n_batch),
         "cpu_baseline": None,
     }
@@ -422,12 +444,16 @@ def bench_serve(args):
     budget = cfg["hbm_budget_bytes"]
     seed = synth.BASE_SEED + 4
 
-    def run(compress, **kw):
+    def run(compress, batch=True, **kw):
         arr = serve.poisson_arrivals(specs, rate, seed, **kw)
-        ex = serve.GpuExecutor(source, nstreams=4, cand_cap=1 << 23)
+        ex = serve.GpuExecutor(source, nstreams=4, cand_cap=1 << 23, batch=batch)
         rep = serve.serve(specs, arr, ex, budget, compress=compress, slots=args.serve_slots)
         s = rep.summary()
         s["compress"] = "inf" if compress == float("inf") else compress
+        s["executor"] = "batched (sps_batch_push)" if batch else "one device stream per beam"
+        if batch:
+            s["gulps_per_launch_max"] = max(ex.batch_sizes) if ex.batch_sizes else 0
+            s["gulps_per_launch_mean"] = (sum(ex.batch_sizes) / len(ex.batch_sizes)) if ex.batch_sizes else 0.0
         s["offered_samples_per_s"] = (sum(specs[a.beam].ndm * specs[a.beam].nsamp for a in arr) /
                                       (max(a.t for a in arr) / compress) if compress != float("inf") else None)
         s["ncand_total"] = int(sum(r.ncand for r in rep.records))
@@ -438,9 +464,10 @@ def bench_serve(args):
         run(float("inf"), gulps_per_beam=2)
     literal = run(1.0, horizon=args.serve_horizon)
     sweep = [run(c, gulps_per_beam=6) for c in (10.0, 30.0, 60.0, 120.0, float("inf"))]
-    if len({s["ncand_total"] for s in sweep}) != 1:
+    per_beam = run(float("inf"), batch=False, gulps_per_beam=6)
+    if len({s["ncand_total"] for s in sweep + [per_beam]}) != 1:
         raise SystemExit("candidate totals differ between serving runs of the same gulps: %s" %
-                         [s["ncand_total"] for s in sweep])
+                         [s["ncand_total"] for s in sweep + [per_beam]])
     sat = sweep[-1]
     out = {
         "metric": "DM-trial-samples/s", "value": sat["samples_per_s"], "unit": "DM-trial-samples/s", "n_gpus": 1,
@@ -449,9 +476,11 @@ def bench_serve(args):
         "config": {"workload": "%s: 16 beams, ndm 512..2048, gulps 2^16..2^18, widths=1..4096, baseline=16384, "
                                "theta=6, Poisson arrivals at %.1fx real time, budget %d B, %d gulps in flight" %
                                (cfg["name"], rate, budget, args.serve_slots),
-                   "value_is": "saturation throughput (all arrivals at once), gulp = step"},
+                   "value_is": "saturation throughput (all arrivals at once), gulp = step",
+                   "executor": "continuous batching: gulps ready together share one launch per stage"},
         "latency_literal_rate": literal,
         "latency_sweep": sweep,
+        "saturation_per_beam_streams": per_beam,
         "cpu_baseline": None,
     }
     print(json.dumps(out))
