@@ -36,10 +36,10 @@ ALU_PAIR_ADD_PEAK_TOPS = 2 * ALU_INT32_PEAK_TOPS
 # was measured on are unchanged (hash of the files below), else null.
 _CSRC = "paper_2512_00398_amd/csrc/"
 KERNEL_SOURCES = {
-    "detect": [_CSRC + "sps_detect.hip", _CSRC + "sps_runs.h", _CSRC + "sps_wave.h", _CSRC + "sps_internal.h",
-               _CSRC + "sps_api.hip", "include/sps.h"],
-    "block_stats": [_CSRC + "sps_stats.hip", _CSRC + "sps_wave.h", _CSRC + "sps_internal.h", _CSRC + "sps_api.hip",
-                    "include/sps.h"],
+    "detect": [_CSRC + "sps_detect.hip", _CSRC + "sps_detect_body.h", _CSRC + "sps_runs.h", _CSRC + "sps_wave.h",
+               _CSRC + "sps_internal.h", _CSRC + "sps_api.hip", "include/sps.h"],
+    "block_stats": [_CSRC + "sps_stats.hip", _CSRC + "sps_chain.h", _CSRC + "sps_wave.h", _CSRC + "sps_internal.h",
+                    _CSRC + "sps_api.hip", "include/sps.h"],
     "dedisp": [_CSRC + "sps_dedisp.hip", _CSRC + "sps_internal.h", _CSRC + "sps_api.hip", "include/sps.h"],
 }
 MEASURED_TRAFFIC = {

@@ -202,6 +202,10 @@ int sps_search_plain(sps_plan* plan, const float* d_series, hipStream_t stream, 
                                      Block medians m_k unchanged. Plans and batches only: streams and
                                      sps_search_plain refuse it. MAD_w above 2^31 - 1 (half the series
                                      more than 2^31 from its median) is taken as 2^31 - 1. */
+#define SPS_ATTR_FUSED 9          /* batches only (tuning): 1 (default) statistics chains and detection in one
+                                     persistent launch, each detection task waiting for its row's chains;
+                                     0 one persistent launch per stage. Only SPS_ATTR_NORM = 0 with
+                                     SPS_ATTR_HIST_BINS = 4096 runs fused; other settings run per stage. */
 #define SPS_ATTR_NBLOCKS 16       /* read-only: ceil(nsamp / 64) */
 #define SPS_ATTR_NWIDTHS 17       /* read-only: number of boxcar widths */
 #define SPS_ATTR_BLOCK_STRIDE 18  /* read-only: S = SPS_BLOCK_STRIDE, part of the arithmetic (never tuned) */
@@ -269,10 +273,12 @@ void sps_stream_destroy(sps_stream* s);
 /*
  * Batch: many independent blocks ("files": the paper processes file after
  * file, Section V; every block is searched exactly as sps_search would search
- * it alone) in one persistent launch per stage. Workgroups take work from a
- * device queue shared by all blocks, whose tasks are ordered largest first,
- * so blocks of very different shapes load-balance with no per-block launch
- * tail.
+ * it alone) in one persistent launch of the statistics chains and the
+ * detection tasks (SPS_ATTR_FUSED = 1), or one persistent launch per stage.
+ * Workgroups take work from device queues shared by all blocks, whose tasks
+ * are ordered largest first, so blocks of very different shapes load-balance
+ * with no per-block launch tail; a small fix-up launch stitches runs across
+ * detection segments.
  *
  * sps_batch_item: one block. d_series device FP32 [ndm][nsamp] (caller-owned,
  *   read-only); parameters obey the sps_plan_create rules; d_cands (capacity
@@ -288,8 +294,9 @@ void sps_stream_destroy(sps_stream* s);
  *   SPS_ERR_INVALID_ARG (any item invalid: nothing enqueued), SPS_ERR_OOM,
  *   SPS_ERR_HIP.
  * sps_batch_set: tuning attributes SPS_ATTR_STATS_SEG, SPS_ATTR_DETECT_SEG,
- *   SPS_ATTR_HIST_BINS, SPS_ATTR_WINDOW and SPS_ATTR_NORM (same meaning as for
- *   plans; apply to every item).
+ *   SPS_ATTR_HIST_BINS and SPS_ATTR_FUSED, and the arithmetic variants
+ *   SPS_ATTR_WINDOW and SPS_ATTR_NORM (same meaning as for plans; apply to
+ *   every item).
  * sps_batch_destroy: waits for the context's work and frees it (NULL-safe).
  */
 typedef struct {

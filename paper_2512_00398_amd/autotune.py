@@ -12,7 +12,8 @@ Results are kept in a JSON file keyed by GPU architecture and shape class
 is SPS_AUTOTUNE_CACHE if set, else ~/.cache/sps/autotune.json.
 
 A batch of blocks (sps_batch_search) is tuned the same way as a whole: the
-same three attributes apply to every item, every configuration must return
+same three attributes, and whether statistics and detection share one
+persistent launch, apply to every item; every configuration must return
 every item's candidate set unchanged, and the result is cached under the
 multiset of the items' shape classes. The fused kernels evaluate every width
 in one pass over the samples, so there is no widths-per-pass attribute.
@@ -30,8 +31,10 @@ import numpy as np
 from . import sps
 
 CACHE_ENV = "SPS_AUTOTUNE_CACHE"
-ATTRS = {"stats_seg": sps.ATTR_STATS_SEG, "detect_seg": sps.ATTR_DETECT_SEG, "hist_bins": sps.ATTR_HIST_BINS}
+ATTRS = {"stats_seg": sps.ATTR_STATS_SEG, "detect_seg": sps.ATTR_DETECT_SEG, "hist_bins": sps.ATTR_HIST_BINS,
+         "fused": sps.ATTR_FUSED}
 DEFAULT = {"stats_seg": 0, "detect_seg": 0, "hist_bins": 4096}
+BATCH_DEFAULT = {"stats_seg": 0, "detect_seg": 0, "hist_bins": 4096, "fused": 1}
 
 
 def _pow2ceil(v: int) -> int:
@@ -202,7 +205,7 @@ def batch_candidate_configs(shapes) -> Dict[str, List[int]]:
     wmax = max(w for _, _, w, _ in shapes)
     nmax = max(n for _, n, _, _ in shapes)
     detect = [0] + [s for s in (16384, 32768, 65536, 131072, 262144) if s >= 4 * wmax and s < nmax]
-    return {"stats_seg": stats, "detect_seg": detect, "hist_bins": [4096, 16384]}
+    return {"stats_seg": stats, "detect_seg": detect, "hist_bins": [4096, 16384], "fused": [1, 0]}
 
 
 def _batch_apply(batch: sps.Batch, cfg: dict) -> None:
@@ -239,7 +242,7 @@ def tune_batch(batch: sps.Batch, items, stream=None, steps: int = 2, path: Optio
     arch = arch or gpu_arch()
     shapes = [(int(x.shape[0]), int(x.shape[1]), int(w), int(L)) for (x, w, L, _, _, _) in items]
     key = batch_key(arch, shapes)
-    best = dict(DEFAULT)
+    best = dict(BATCH_DEFAULT)
     _batch_apply(batch, best)
     best_ms, ref = _batch_measure(batch, items, stream, steps)
     default_ms = best_ms

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsps.so")
-SOURCES = ["sps_api.hip", "sps_stats.hip", "sps_detect.hip", "sps_plain.hip", "sps_cluster.hip", "sps_rownorm.hip", "sps_widthnorm.hip", "sps_dedisp.hip", "sps_rfi.hip"]
+SOURCES = ["sps_api.hip", "sps_stats.hip", "sps_detect.hip", "sps_fused.hip", "sps_plain.hip", "sps_cluster.hip", "sps_rownorm.hip", "sps_widthnorm.hip", "sps_dedisp.hip", "sps_rfi.hip"]
 
 HIPCC_FLAGS = [
     "-O3",

@@ -473,6 +473,7 @@ static int launch_stats(sps_plan* p, const float* d_series, hipStream_t stream, 
   a.tmin = nullptr;
   a.med = d_median;
   a.mad = d_mad;
+  a.done = nullptr;
   if (sps::launch_block_stats(a, p->hist_bins, stream) != hipSuccess) return fail(SPS_ERR_HIP);
   if (p->norm == 1) {
     const sps::RowMadArgs r{d_series, p->nsamp, p->nsamp, p->nblocks, p->ndm, d_median, d_mad};
@@ -533,6 +534,8 @@ static int enqueue_search(sps_plan* p, const float* d_series, hipStream_t stream
   d.ncand = d_ncand;
   d.cap = (uint32_t)p->max_cands;
   d.frag = frag;
+  d.done = nullptr;
+  d.done_target = 0;
   if (sps::launch_detect(d, stream) != hipSuccess) return SPS_ERR_HIP;
   hipEvent_t e3 = mark(p, stream);
   if (sps::launch_fixup(d, stream) != hipSuccess) return SPS_ERR_HIP;
@@ -935,6 +938,7 @@ sps::StatsArgs stream_stats_args(const sps_stream* s, const float* d_gulp, int c
   a.tmin = s->tmin;
   a.med = s->med[c];
   a.mad = s->mad[c];
+  a.done = nullptr;
   return a;
 }
 
@@ -971,6 +975,8 @@ sps::DetectArgs stream_detect_args(const sps_stream* s, const float* d_gulp, sps
   d.ncand = d_ncand;
   d.cap = (uint32_t)p->max_cands;
   d.frag = s->frag;
+  d.done = nullptr;
+  d.done_target = 0;
   return d;
 }
 
@@ -1203,6 +1209,7 @@ struct sps_batch {
   int32_t stats_seg, detect_seg, hist_bins;
   int32_t window;      // SPS_ATTR_WINDOW for every item
   int32_t norm;        // SPS_ATTR_NORM for every item
+  int32_t fused;       // SPS_ATTR_FUSED: statistics and detection in one persistent launch
   int32_t* d_ms;       // medians then MADs of every item (then per-width c_w and MAD_w with SPS_ATTR_NORM = 2)
   int64_t ms_cap;      // int32 records
   sps::RunSum* d_frag;
@@ -1215,6 +1222,7 @@ struct sps_batch {
   bool pending;        // both events recorded at least once
   int grid_stats[2];   // resident workgroups: 4096 / 16384 bins (0 = not queried)
   int grid_detect[2];  // 13 widths / any
+  int grid_search[2];  // fused kernel: 13 widths / any
 };
 
 namespace {
@@ -1318,6 +1326,7 @@ int sps_batch_create(sps_batch** out) {
   if (!b) return fail(SPS_ERR_OOM);
   std::memset(b, 0, sizeof(*b));
   b->hist_bins = 4096;
+  b->fused = 1;
   if (hipGetDevice(&b->device) != hipSuccess ||
       hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
@@ -1352,6 +1361,10 @@ int sps_batch_set(sps_batch* b, int attr, int64_t v) {
     case SPS_ATTR_NORM:
       if (v < 0 || v > 2) return fail(SPS_ERR_INVALID_ARG);
       b->norm = (int32_t)v;
+      return ok();
+    case SPS_ATTR_FUSED:
+      if (v != 0 && v != 1) return fail(SPS_ERR_INVALID_ARG);
+      b->fused = (int32_t)v;
       return ok();
     default:
       return fail(SPS_ERR_INVALID_ARG);
@@ -1426,6 +1439,13 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
       fix_total += (int64_t)it.ndm * s.nw;
     }
   }
+  // Fused launch (statistics chains then detection in one persistent kernel):
+  // per row of every item a count of its finished chains, after the medians.
+  const bool fused = b->fused == 1 && b->norm == 0 && b->hist_bins == 4096;
+  int64_t total_rows = 0;
+  for (int32_t i = 0; i < n; ++i) total_rows += items[i].ndm;
+  const int64_t done_off = ms_need;
+  if (fused) ms_need += total_rows;
   // task counts must fit the int32 queue
   int64_t stats_total = 0, detect_total = 0;
   for (const BatchShape& s : sh) {
@@ -1460,6 +1480,14 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
   auto* fo = reinterpret_cast<int32_t*>(h + off_fo);
   auto* np = reinterpret_cast<uint32_t**>(h + off_np);
 
+  std::vector<int64_t> row0((size_t)n);
+  {
+    int64_t r = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      row0[(size_t)i] = r;
+      r += items[i].ndm;
+    }
+  }
   // Stats queue: longest chains (warm-up window + segment) first.
   std::vector<BatchShape> ord = sh;
   std::stable_sort(ord.begin(), ord.end(), [&](const BatchShape& x, const BatchShape& y) {
@@ -1489,6 +1517,7 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
     a.tmin = nullptr;
     a.med = b->d_ms + s.ms_off;
     a.mad = b->d_ms + s.ms_off + (int64_t)it.ndm * s.nblocks;
+    a.done = fused ? reinterpret_cast<uint32_t*>(b->d_ms + done_off + row0[(size_t)s.idx]) : nullptr;
     if (b->norm == 1) row_mads.push_back(sps::RowMadArgs{a.x, a.ld, a.N, a.nblocks, it.ndm, a.med, a.mad});
     if (b->norm == 2)
       width_stats.push_back(sps::WidthStatsArgs{a.x, a.ld, a.N, a.nblocks, it.ndm, s.nw, a.med, b->d_ms + s.ws_off,
@@ -1537,6 +1566,8 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
     a.ncand = it.d_ncand;
     a.cap = (uint32_t)it.max_cands;
     a.frag = s.detect_nseg > 1 ? b->d_frag + s.frag_off : nullptr;
+    a.done = fused ? reinterpret_cast<const uint32_t*>(b->d_ms + done_off + row0[(size_t)s.idx]) : nullptr;
+    a.done_target = (uint32_t)s.stats_nseg;
     dof[k] = acc;
     acc += it.ndm * s.detect_nseg;
     fo[k] = facc;
@@ -1557,12 +1588,23 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
   const int wpg = b->hist_bins == 16384 ? 2 : 4;
   const int gs = (int)std::min<int64_t>(b->grid_stats[bins], (bs.total + wpg - 1) / wpg);
   const int gd = (int)std::min<int64_t>(b->grid_detect[all13 ? 0 : 1], bd.total);
-  if (sps::launch_batch_zero(reinterpret_cast<uint32_t* const*>(d + off_np), n, counters, stream) != hipSuccess ||
-      sps::launch_block_stats_batch(bs, b->hist_bins, b->window == 1, false, gs, stream) != hipSuccess ||
-      launch_row_mads(row_mads, stream) != hipSuccess || launch_width_stats_all(width_stats, stream) != hipSuccess ||
-      sps::launch_detect_batch(bd, all13 ? 13 : 0, false, gd, stream) != hipSuccess ||
-      sps::launch_fixup_batch(bd, reinterpret_cast<const int32_t*>(d + off_fo), fo[n], stream) != hipSuccess ||
-      hipEventRecord(b->done, stream) != hipSuccess) {
+  bool okl = sps::launch_batch_zero(reinterpret_cast<uint32_t* const*>(d + off_np), n, counters, stream) == hipSuccess;
+  if (fused) {
+    const int k13 = all13 ? 0 : 1;
+    if (!b->grid_search[k13]) b->grid_search[k13] = sps::search_batch_grid(all13 ? 13 : 0);
+    const int gf = (int)std::min<int64_t>(b->grid_search[k13], std::max<int64_t>((bs.total + 3) / 4, bd.total));
+    okl = okl && b->grid_search[k13] > 0 &&
+          sps::launch_zero_u32(reinterpret_cast<uint32_t*>(b->d_ms + done_off), (int)total_rows, stream) == hipSuccess &&
+          sps::launch_search_batch(bs, bd, all13 ? 13 : 0, b->window == 1, gf, stream) == hipSuccess;
+  } else {
+    okl = okl && sps::launch_block_stats_batch(bs, b->hist_bins, b->window == 1, false, gs, stream) == hipSuccess &&
+          launch_row_mads(row_mads, stream) == hipSuccess && launch_width_stats_all(width_stats, stream) == hipSuccess &&
+          sps::launch_detect_batch(bd, all13 ? 13 : 0, false, gd, stream) == hipSuccess;
+  }
+  okl = okl && sps::launch_fixup_batch(bd, reinterpret_cast<const int32_t*>(d + off_fo), fo[n], stream) == hipSuccess &&
+        hipEventRecord(b->done, stream) == hipSuccess;
+  if (!okl) {
+    (void)hipGetLastError();
     b->pending = true;
     return fail(SPS_ERR_HIP);
   }

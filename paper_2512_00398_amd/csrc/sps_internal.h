@@ -56,6 +56,7 @@ struct StatsArgs {
   const int32_t* tmin; // device: no window reaches below *tmin (null: 0)
   int32_t* med;        // [rows][nblocks]
   int32_t* mad;
+  uint32_t* done;      // fused batch: per row, chains finished (null elsewhere)
 };
 
 // One scale per row: MAD of the row's residual (against med) about its
@@ -164,6 +165,8 @@ struct DetectArgs {
   uint32_t* ncand;
   uint32_t cap;
   RunSum* frag;        // [rows][nw][nseg] summaries of segment edges
+  const uint32_t* done;  // fused batch: per row, chains finished (null elsewhere)
+  uint32_t done_target;  // chains per row
 };
 
 // Streaming: fold one push's segment summaries into the carried per-(row,
@@ -264,6 +267,11 @@ hipError_t launch_detect_batch(const BatchDetect& b, int nw_all, bool virt, int 
 int detect_batch_grid(int nw_all);
 hipError_t launch_fixup_batch(const BatchDetect& b, const int32_t* d_offs, int total, hipStream_t s);
 hipError_t launch_batch_zero(uint32_t* const* d_ncand, int n, uint32_t* counters, hipStream_t s);
+// Fused batch: statistics chains, then detection tasks that wait on their
+// rows' chains, in one persistent launch (4096-bin histograms).
+hipError_t launch_search_batch(const BatchStats& bs, const BatchDetect& bd, int nw_all, bool lead, int grid,
+                               hipStream_t s);
+int search_batch_grid(int nw_all);
 hipError_t launch_plain_prepare(const PlainArgs& a, hipStream_t s);
 hipError_t launch_plain_width(const PlainArgs& a, hipStream_t s);
 hipError_t launch_cluster(const sps_cand* c, uint32_t n, int time_tol, int dm_tol, int width_tol,

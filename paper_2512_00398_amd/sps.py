@@ -32,6 +32,7 @@ ATTR_TIMING = 5
 ATTR_VALIDATE = 6
 ATTR_WINDOW = 7  # 0 trailing baseline window (default), 1 centred on its block
 ATTR_NORM = 8  # 0 per-block MAD scale (default), 1 one MAD per DM row, 2 one MAD per (DM row, width)
+ATTR_FUSED = 9  # batches: 1 (default) statistics and detection in one persistent launch, 0 one per stage
 NSTAGES = 4
 STAGES = ("block_stats", "detect", "fixup", "plain")
 ATTR_NBLOCKS = 16

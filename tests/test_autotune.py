@@ -93,6 +93,7 @@ def test_batch_candidate_configs_fit_the_items():
     assert all(s >= 4 * 4096 and s < (1 << 20) for s in c["detect_seg"][1:])
     assert all(s < (1 << 20) // 64 for s in c["stats_seg"][1:])
     assert sorted(c["hist_bins"]) == [4096, 16384]
+    assert sorted(c["fused"]) == [0, 1]
 
 
 @pytest.mark.gpu

@@ -155,3 +155,29 @@ def test_batch_workload_files_sampled():
             sel = got[got["dm_idx"] == r]
             assert compare_cands(sel, ref, b.snr_thresh, "file %d row %d" % (pick[k], r)) == 0
             assert exact_equal(sel, ref), (k, r)
+
+
+def test_fused_launch_equals_per_stage_launches_and_oracle():
+    # SPS_ATTR_FUSED = 1 (the default) runs the statistics chains and the
+    # detection tasks in one persistent launch, each task waiting for its
+    # row's chains; 0 runs one launch per stage. Both give each block's own
+    # result, also with the centred window, more chains than resident waves,
+    # and settings that fall back to per-stage launches (16384 bins).
+    import torch
+    m = sps()
+    blocks = mixed_blocks()
+    xs = [torch.from_numpy(synth.generate(b)).cuda() for b in blocks]
+    refs = [oracle.search(x.cpu().numpy(), b.max_width, b.baseline_len, b.snr_thresh) for b, x in zip(blocks, xs)]
+    for tune in ({m.ATTR_FUSED: 1}, {m.ATTR_FUSED: 0}, {m.ATTR_FUSED: 1, m.ATTR_STATS_SEG: 64},
+                 {m.ATTR_FUSED: 1, m.ATTR_HIST_BINS: 16384}, {m.ATTR_FUSED: 1, m.ATTR_DETECT_SEG: 1024}):
+        got = run_batch(blocks, xs, tune=tune)
+        for k, (g, r) in enumerate(zip(got, refs)):
+            assert exact_equal(as_oracle(g), r), (tune, k)
+    for fused in (1, 0):
+        got = run_batch(blocks, xs, tune={m.ATTR_FUSED: fused, m.ATTR_WINDOW: 1})
+        for k, (g, b, x) in enumerate(zip(got, blocks, xs)):
+            ref = oracle.search(x.cpu().numpy(), b.max_width, b.baseline_len, b.snr_thresh, centered=True)
+            assert exact_equal(as_oracle(g), ref), ("centred", fused, k)
+    with pytest.raises(m.SpsError):
+        with m.Batch() as b:
+            b.set(m.ATTR_FUSED, 2)
