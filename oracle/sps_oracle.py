@@ -45,7 +45,11 @@ design notes):
     is computed as before, and every block of the row takes the one value
     ``MAD_row`` = lower median of ``|r_t - c|`` over the whole row, where
     ``c`` is the lower median of ``r_t``; items 6-7 then use it in place of
-    ``MAD_{k*}``. The medians ``m_k`` are unchanged.
+    ``MAD_{k*}``. The medians ``m_k`` are unchanged. In a stream the chunk
+    is the gulp (gulps hold whole blocks): every block of gulp g takes the
+    ``MAD_row`` of the residuals ``r_t`` whose t lies in gulp g, the
+    residuals being those of item 5 on the concatenation (trailing windows
+    reach back into earlier gulps).
 11. Per-width re-normalisation variant (a plan option; Section II-B's
     normalisation read as a scale for every filtered series, the way
     Heimdall re-normalises each boxcar output): the residual and boxcar sums
@@ -198,15 +202,33 @@ def peaks(above: np.ndarray, snr: np.ndarray) -> List[Tuple[int, float]]:
     return out
 
 
+def gulp_row_mads(r: np.ndarray, gulp_len: int, stride: int = BLOCK_STRIDE) -> np.ndarray:
+    """Reading 10 in a stream: block k takes the row MAD of the residuals of the gulp holding it."""
+    if gulp_len <= 0 or gulp_len % stride:
+        raise ValueError("gulps hold whole blocks")
+    nb = (r.size + stride - 1) // stride
+    per_gulp = gulp_len // stride
+    out = np.empty(nb, dtype=np.int64)
+    for g0 in range(0, r.size, gulp_len):
+        k0 = g0 // stride
+        out[k0:k0 + per_gulp] = row_mad(r[g0:g0 + gulp_len])
+    return out
+
+
 def search_row(x_row: np.ndarray, dm_idx: int, max_width: int, baseline_len: int, theta: float,
                stride: int = BLOCK_STRIDE, with_stats: bool = False, lead: int = 0, row_norm: bool = False,
-               width_norm: bool = False):
-    """Stages of one DM trial in the paper's order: baseline, normalise, filter, detect."""
+               width_norm: bool = False, gulp_len: int = 0):
+    """Stages of one DM trial in the paper's order: baseline, normalise, filter, detect.
+
+    ``gulp_len`` > 0 with ``row_norm``: one scale per gulp of that length
+    (reading 10 in a stream)."""
     if row_norm and width_norm:
         raise ValueError("row_norm and width_norm are alternative readings")
     m, mad = block_median_mad(x_row, baseline_len, stride, lead)
     r = residual(x_row, m, stride)
-    if row_norm:
+    if row_norm and gulp_len > 0:
+        mad = gulp_row_mads(r, gulp_len, stride)
+    elif row_norm:
         mad = np.full(mad.size, row_mad(r), dtype=np.int64)
     cands = []
     for w in widths(max_width):
@@ -252,14 +274,15 @@ def sort_cands(c: np.ndarray) -> np.ndarray:
 def search(block: np.ndarray, max_width: int, baseline_len: int, theta: float,
            rows: Optional[Iterable[int]] = None, stride: int = BLOCK_STRIDE,
            row_ids: Optional[Sequence[int]] = None, with_stats: bool = False, centered: bool = False,
-           row_norm: bool = False, width_norm: bool = False):
+           row_norm: bool = False, width_norm: bool = False, gulp_len: int = 0):
     """Search every row of ``block`` ([ndm][N]); candidates sorted (dm, width, sample).
 
     ``rows`` restricts the search to those rows of ``block``; ``row_ids``
     gives the DM index reported for each row of ``block`` (default: the row's
     position). With ``with_stats`` also returns int64 ``m`` and ``mad`` of
     shape ``[len(rows)][ceil(N/S)]``. ``centered``, ``row_norm`` and
-    ``width_norm`` select readings 9, 10 and 11.
+    ``width_norm`` select readings 9, 10 and 11; ``gulp_len`` > 0 with
+    ``row_norm`` takes one row scale per gulp of that length.
     """
     block = np.asarray(block)
     if block.ndim != 2:
@@ -270,7 +293,7 @@ def search(block: np.ndarray, max_width: int, baseline_len: int, theta: float,
         d = r if row_ids is None else int(row_ids[r])
         c, m, mad = search_row(block[r], d, max_width, baseline_len, theta, stride, with_stats=True,
                                lead=window_lead(baseline_len, stride, centered), row_norm=row_norm,
-                               width_norm=width_norm)
+                               width_norm=width_norm, gulp_len=gulp_len)
         parts.append(c)
         ms.append(m)
         mads.append(mad)
@@ -282,9 +305,15 @@ def search(block: np.ndarray, max_width: int, baseline_len: int, theta: float,
 
 
 def search_stream(gulps: Sequence[np.ndarray], max_width: int, baseline_len: int, theta: float,
-                  stride: int = BLOCK_STRIDE) -> np.ndarray:
-    """Reading 8: streaming equals the one-shot search of the concatenated gulps (global sample index)."""
-    return search(np.concatenate(list(gulps), axis=1), max_width, baseline_len, theta, stride=stride)
+                  stride: int = BLOCK_STRIDE, row_norm: bool = False) -> np.ndarray:
+    """Reading 8: streaming equals the one-shot search of the concatenated gulps (global sample index).
+
+    ``row_norm``: reading 10 per gulp (the gulps must have one length)."""
+    gulps = list(gulps)
+    if row_norm and len({g.shape[1] for g in gulps}) > 1:
+        raise ValueError("a stream's gulps have one length")
+    return search(np.concatenate(gulps, axis=1), max_width, baseline_len, theta, stride=stride, row_norm=row_norm,
+                  gulp_len=gulps[0].shape[1] if row_norm else 0)
 
 
 def search_batch(items: Sequence[Tuple[np.ndarray, int, int, float]], stride: int = BLOCK_STRIDE) -> List[np.ndarray]:

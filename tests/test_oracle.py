@@ -33,17 +33,22 @@ def brute_stats(x, L, S):
     return ms, mads
 
 
-def brute_search_row(x, dm, max_width, L, theta, S, row_norm=False, width_norm=False):
+def brute_search_row(x, dm, max_width, L, theta, S, row_norm=False, width_norm=False, gulp_len=0):
     """Whole search for one row with explicit loops only (row_norm: one MAD
-    for the row, of the residual about its lower median; width_norm: one MAD
-    per width, of the boxcar sums about their lower median, and no sqrt(w))."""
+    for the row, of the residual about its lower median, or with gulp_len
+    one such MAD per gulp for the gulp's blocks; width_norm: one MAD per
+    width, of the boxcar sums about their lower median, and no sqrt(w))."""
     ms, mads = brute_stats(x, L, S)
     n = len(x)
     r = [x[t] - ms[t // S] for t in range(n)]
     if row_norm:
-        sr = sorted(r)
-        c = sr[(n - 1) // 2]
-        mads = [sorted(abs(v - c) for v in r)[(n - 1) // 2]] * len(mads)
+        g = gulp_len if gulp_len else n
+        mads = []
+        for g0 in range(0, n, g):
+            part = r[g0:g0 + g]
+            c = sorted(part)[(len(part) - 1) // 2]
+            d = sorted(abs(v - c) for v in part)[(len(part) - 1) // 2]
+            mads += [d] * ((len(part) + S - 1) // S)
     th = float(np.float32(theta))
     out = []
     w = 1
@@ -339,6 +344,52 @@ def test_row_norm_brute_force(n, L, S, maxw, theta, seed):
     _, _, mad = oracle.search_row(x, 5, maxw, L, theta, S, with_stats=True)
     _, _, rmad = oracle.search_row(x, 5, maxw, L, theta, S, with_stats=True, row_norm=True)
     assert np.all(rmad == rmad[0]) and not np.array_equal(mad, rmad)
+
+
+@pytest.mark.parametrize("gulp,ngulps,L,S,maxw,theta,seed", [(64, 4, 50, 8, 16, 3.0, 0), (96, 3, 150, 16, 32, 2.5, 1),
+                                                            (128, 2, 300, 64, 8, 3.0, 2), (40, 5, 17, 8, 64, 2.0, 3)])
+def test_row_norm_per_gulp_brute_force(gulp, ngulps, L, S, maxw, theta, seed):
+    # a stream takes one row scale per gulp; gulps of very different noise
+    rng = np.random.default_rng(700 + seed)
+    parts = [rng.integers(-a, a + 1, size=(2, gulp)) for a in (5, 60, 9, 200, 30)[:ngulps]]
+    parts[-1][:, gulp // 2:gulp // 2 + 3] += 500
+    got = oracle.search_stream([p.astype(np.float32) for p in parts], maxw, L, theta, stride=S, row_norm=True)
+    x = np.concatenate(parts, axis=1)
+    want = []
+    for row in range(2):
+        want += brute_search_row(x[row].tolist(), row, maxw, L, theta, S, row_norm=True, gulp_len=gulp)
+    assert as_tuples(got) == sorted(want, key=lambda c: (c[1], c[2], c[0]))
+    assert len(want) > 0
+
+
+def test_row_norm_one_gulp_is_the_row_scale():
+    rng = np.random.default_rng(71)
+    x = rng.integers(-50, 51, size=(3, 640)).astype(np.float32)
+    x[:, 300:305] += 400
+    one = oracle.search_stream([x], 32, 200, 3.0, row_norm=True)
+    assert np.array_equal(one, oracle.search(x, 32, 200, 3.0, row_norm=True))
+    assert one.size > 0
+
+
+def test_row_norm_per_gulp_scales_follow_each_gulp():
+    # uniform integers on [-a, a] about a zero baseline: the MAD of a long gulp
+    # is close to a/2, so the per-gulp scales track each gulp's noise
+    rng = np.random.default_rng(72)
+    n = 64 * 400
+    x = np.concatenate([rng.integers(-a, a + 1, size=n) for a in (10, 100, 40)])
+    m, _ = oracle.block_median_mad(x, 64 * 8)
+    r = oracle.residual(x, m)
+    mads = oracle.gulp_row_mads(r, n)
+    per = n // 64
+    for g, a in enumerate((10, 100, 40)):
+        blk = mads[g * per:(g + 1) * per]
+        assert np.all(blk == blk[0])
+        assert abs(blk[0] - a / 2) <= 0.1 * a
+    with pytest.raises(ValueError):
+        oracle.gulp_row_mads(r, 100)  # gulps hold whole blocks
+    with pytest.raises(ValueError):
+        oracle.search_stream([x[None, :640].astype(np.float32), x[None, :704].astype(np.float32)], 8, 64, 3.0,
+                             row_norm=True)
 
 
 def test_row_norm_shift_and_scale_invariance():
