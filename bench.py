@@ -45,8 +45,8 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md,
     # profiles/dedisp_1024ch_1024dm_2p18.md
-    "detect": ("a887b5a488378cb8", (2237779 * 2 + 170185) * 1024),
-    "block_stats": ("2e9d5d2d1e7f0a73", (4349788 * 2 + 137113) * 1024),
+    "detect": ("e67eec6696954a69", (2237782 * 2 + 170188) * 1024),
+    "block_stats": ("1d6a769e771e8b3c", (4349769 * 2 + 137136) * 1024),
     "dedisp": ("a0a762ea61972dd1", (3436542 * 2 + 1048576) * 1024),
 }
 
@@ -55,6 +55,9 @@ MEASURED_TRAFFIC = {
 # SQ_INSTS_VALU (profiles/); reported only while the sources are unchanged.
 VALU_ISSUE_PER_S = 256 * 2.4e9
 MEASURED_VALU = {
+    # kernel: (sources hash, SQ_INSTS_VALU per launch); profiles/kernels_c2_1024x2p20.md
+    "detect": ("e67eec6696954a69", 3.311e9),
+    "block_stats": ("1d6a769e771e8b3c", 1.875e9),
 }
 
 

@@ -191,8 +191,10 @@ int sps_search_plain(sps_plan* plan, const float* d_series, hipStream_t stream, 
                                      1 one scale per DM row, MAD_row = lower median of |r_t - c| over the
                                      whole row, r_t = x_t - m_{t/64} and c the lower median of r (Section
                                      II-B's normalisation read as one scale per trial and chunk). Every
-                                     block of the row then reports and uses MAD_row. Plans and batches; a
-                                     stream refuses a plan with 1 (the row is not complete in one gulp). */
+                                     block of the row then reports and uses MAD_row. Plans and batches;
+                                     in a stream the chunk is the gulp: every block of a gulp takes the
+                                     MAD_row of that gulp's residuals (residuals as on the concatenation,
+                                     trailing windows reaching into earlier gulps). */
                                   /* 2 one scale per (DM row, width): for the boxcar-filtered series
                                      T_w = {S_w(i) : 0 <= i <= nsamp - w}, c_w = lower median of T_w
                                      and MAD_w = lower median of |S_w(i) - c_w|; then
@@ -239,8 +241,9 @@ int sps_timing_read(sps_plan* plan, double* ms_out, int64_t* nsearch);
  * sps_stream_create: `plan` gives the gulp shape (ndm x nsamp, nsamp a
  *   multiple of 64) and parameters; it must outlive the stream, and the
  *   stream must not run concurrently with another use of the plan. A plan
- *   with SPS_ATTR_WINDOW = 1 or SPS_ATTR_NORM = 1 is refused
- *   (SPS_ERR_INVALID_ARG).
+ *   with SPS_ATTR_WINDOW = 1 or SPS_ATTR_NORM = 2 is refused
+ *   (SPS_ERR_INVALID_ARG), here and at every push if the plan's attributes
+ *   were changed since; SPS_ATTR_NORM = 1 gives one row scale per gulp.
  * sps_stream_push: search one gulp (device FP32 [ndm][nsamp]); candidates are
  *   those whose runs ended during this gulp, with `sample` relative to the
  *   gulp's first sample (negative: the boxcar started in an earlier gulp).

@@ -476,7 +476,7 @@ static int launch_stats(sps_plan* p, const float* d_series, hipStream_t stream, 
   a.done = nullptr;
   if (sps::launch_block_stats(a, p->hist_bins, stream) != hipSuccess) return fail(SPS_ERR_HIP);
   if (p->norm == 1) {
-    const sps::RowMadArgs r{d_series, p->nsamp, p->nsamp, p->nblocks, p->ndm, d_median, d_mad};
+    const sps::RowMadArgs r{d_series, p->nsamp, p->nsamp, p->nblocks, p->nblocks, p->ndm, d_median, d_mad};
     if (sps::launch_row_mad(r, stream) != hipSuccess) return fail(SPS_ERR_HIP);
   }
   return ok();
@@ -744,6 +744,7 @@ struct sps_stream {
   hipStream_t cap_stream;
   struct GraphEntry {
     const void* key[3];
+    int32_t norm;  // the scale the graph was captured with
     hipGraphExec_t exec[2];
     uint64_t last_use;
   } graphs[kGraphCache];
@@ -764,6 +765,11 @@ struct StreamHeader {
 constexpr uint64_t kStreamMagic = 0x5350535354524D32ull;  // "SPSSTRM2"
 
 // History length, virtual row and detection segments of a stream on plan p.
+// Arithmetic a stream can run: the trailing window (a centred one would wait
+// for the next gulp), with the block scale or one row scale per gulp (the
+// per-width scale needs the whole filtered series).
+bool stream_plan_ok(const sps_plan* p) { return p->window == 0 && p->norm != 2; }
+
 bool stream_geometry(const sps_plan* p, sps_stream* s) {
   const int64_t need = std::max<int64_t>(p->baseline_len, p->max_width);
   s->Hx = (int32_t)((need + kDetectStep - 1) / kDetectStep * kDetectStep);
@@ -872,8 +878,7 @@ int sps_stream_create(sps_plan* p, sps_stream** out) {
   if (!p || !out) return fail(SPS_ERR_INVALID_ARG);
   *out = nullptr;
   if (p->nsamp % sps::kStride != 0) return fail(SPS_ERR_INVALID_ARG);  // gulps must hold whole blocks
-  if (p->window != 0) return fail(SPS_ERR_INVALID_ARG);  // a centred window would wait for the next gulp
-  if (p->norm != 0) return fail(SPS_ERR_INVALID_ARG);    // a row scale needs the whole row
+  if (!stream_plan_ok(p)) return fail(SPS_ERR_INVALID_ARG);
   sps_stream* s = new (std::nothrow) sps_stream;
   if (!s) return fail(SPS_ERR_OOM);
   std::memset(s, 0, sizeof(*s));
@@ -942,6 +947,14 @@ sps::StatsArgs stream_stats_args(const sps_stream* s, const float* d_gulp, int c
   return a;
 }
 
+// One row scale per gulp (SPS_ATTR_NORM = 1): the row MAD of the gulp's
+// residuals, written to the gulp's blocks of history buffer c.
+sps::RowMadArgs stream_row_mad_args(const sps_stream* s, const float* d_gulp, int c) {
+  const sps_plan* p = s->plan;
+  return sps::RowMadArgs{d_gulp, p->nsamp, (int32_t)p->nsamp, s->nbv - s->Hb, s->nbv, p->ndm,
+                         s->med[c] + s->Hb, s->mad[c] + s->Hb};
+}
+
 // Detection of one gulp of stream s reading history buffer c: window ends
 // inside the gulp; runs at segment edges are left to k_stream_fold.
 sps::DetectArgs stream_detect_args(const sps_stream* s, const float* d_gulp, sps_cand* d_cands, uint32_t* d_ncand,
@@ -996,6 +1009,8 @@ int stream_enqueue(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_c
   hipEvent_t e1 = mark(p, stream);
   const sps::StatsArgs a = stream_stats_args(s, d_gulp, c);
   if (sps::launch_block_stats(a, p->hist_bins, stream) != hipSuccess) return SPS_ERR_HIP;
+  if (p->norm == 1 && sps::launch_row_mad(stream_row_mad_args(s, d_gulp, c), stream) != hipSuccess)
+    return SPS_ERR_HIP;
   hipEvent_t e2 = mark(p, stream);
   const sps::DetectArgs d = stream_detect_args(s, d_gulp, d_cands, d_ncand, c);
   if (sps::launch_detect(d, stream) != hipSuccess) return SPS_ERR_HIP;
@@ -1025,6 +1040,7 @@ extern "C" {
 int sps_stream_push(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands, uint32_t* d_ncand,
                     int64_t* gulp_offset) {
   if (!s || !d_gulp || !d_ncand || (!d_cands && s->plan->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+  if (!stream_plan_ok(s->plan)) return fail(SPS_ERR_INVALID_ARG);  // attributes changed since create
   {
     const int rc = check_domain(s->plan, d_gulp, (int64_t)s->plan->ndm * s->plan->nsamp, stream);
     if (rc != SPS_OK) return fail(rc);
@@ -1041,13 +1057,15 @@ int sps_stream_push(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_
 int sps_stream_push_graph(sps_stream* s, const float* d_gulp, hipStream_t stream, sps_cand* d_cands,
                           uint32_t* d_ncand, int64_t* gulp_offset) {
   if (!s || !d_gulp || !d_ncand || (!d_cands && s->plan->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+  if (!stream_plan_ok(s->plan)) return fail(SPS_ERR_INVALID_ARG);  // attributes changed since create
   {
     const int rc = check_domain(s->plan, d_gulp, (int64_t)s->plan->ndm * s->plan->nsamp, stream);
     if (rc != SPS_OK) return fail(rc);
   }
   sps_stream::GraphEntry* hit = nullptr;
   for (auto& e : s->graphs)
-    if (e.exec[0] && e.key[0] == d_gulp && e.key[1] == d_cands && e.key[2] == d_ncand) hit = &e;
+    if (e.exec[0] && e.key[0] == d_gulp && e.key[1] == d_cands && e.key[2] == d_ncand && e.norm == s->plan->norm)
+      hit = &e;
   if (!hit) {
     for (auto& e : s->graphs)
       if (!e.exec[0]) {
@@ -1091,6 +1109,7 @@ int sps_stream_push_graph(sps_stream* s, const float* d_gulp, hipStream_t stream
     hit->key[0] = d_gulp;
     hit->key[1] = d_cands;
     hit->key[2] = d_ncand;
+    hit->norm = s->plan->norm;
   }
   hit->last_use = ++s->graph_clock;
   if (hipGraphLaunch(hit->exec[s->cur], stream) != hipSuccess) return fail(SPS_ERR_HIP);
@@ -1518,7 +1537,7 @@ int sps_batch_search(sps_batch* b, const sps_batch_item* items, int32_t n, hipSt
     a.med = b->d_ms + s.ms_off;
     a.mad = b->d_ms + s.ms_off + (int64_t)it.ndm * s.nblocks;
     a.done = fused ? reinterpret_cast<uint32_t*>(b->d_ms + done_off + row0[(size_t)s.idx]) : nullptr;
-    if (b->norm == 1) row_mads.push_back(sps::RowMadArgs{a.x, a.ld, a.N, a.nblocks, it.ndm, a.med, a.mad});
+    if (b->norm == 1) row_mads.push_back(sps::RowMadArgs{a.x, a.ld, a.N, a.nblocks, a.nblocks, it.ndm, a.med, a.mad});
     if (b->norm == 2)
       width_stats.push_back(sps::WidthStatsArgs{a.x, a.ld, a.N, a.nblocks, it.ndm, s.nw, a.med, b->d_ms + s.ws_off,
                                                 b->d_ms + s.ws_off + (int64_t)it.ndm * s.nw});
@@ -1620,6 +1639,7 @@ int sps_batch_push(sps_batch* b, sps_stream* const* streams, const float* const*
   for (int32_t i = 0; i < n; ++i) {
     const sps_stream* s = streams[i];
     if (!s || !d_gulps[i] || !d_ncand[i] || (!d_cands[i] && s->plan->max_cands > 0)) return fail(SPS_ERR_INVALID_ARG);
+    if (!stream_plan_ok(s->plan)) return fail(SPS_ERR_INVALID_ARG);
     for (int32_t k = 0; k < i; ++k)
       if (streams[k] == s) return fail(SPS_ERR_INVALID_ARG);  // one gulp per stream: the next needs this one's carry
     all13 = all13 && s->plan->nw == sps::kMaxWidths;
@@ -1692,8 +1712,12 @@ int sps_batch_push(sps_batch* b, sps_stream* const* streams, const float* const*
   const int gs = (int)std::min<int64_t>(b->grid_stats[bins], (bs.total + wpg - 1) / wpg);
   const int gd = (int)std::min<int64_t>(b->grid_detect[all13 ? 0 : 1], bd.total);
   bool okl = sps::launch_batch_zero(reinterpret_cast<uint32_t* const*>(d + off_np), n, counters, stream) == hipSuccess &&
-             sps::launch_block_stats_batch(bs, b->hist_bins, false, true, gs, stream) == hipSuccess &&
-             sps::launch_detect_batch(bd, all13 ? 13 : 0, true, gd, stream) == hipSuccess;
+             sps::launch_block_stats_batch(bs, b->hist_bins, false, true, gs, stream) == hipSuccess;
+  // streams with one row scale per gulp: the gulp's row MAD before detection
+  for (int32_t i = 0; okl && i < n; ++i)
+    if (streams[i]->plan->norm == 1)
+      okl = sps::launch_row_mad(stream_row_mad_args(streams[i], d_gulps[i], streams[i]->cur), stream) == hipSuccess;
+  okl = okl && sps::launch_detect_batch(bd, all13 ? 13 : 0, true, gd, stream) == hipSuccess;
   // each stream folds its open runs and rolls its history forward
   for (int32_t i = 0; okl && i < n; ++i) {
     const sps::StreamArgs fa = stream_args(streams[i], d_gulps[i], d_cands[i], d_ncand[i]);

@@ -65,10 +65,11 @@ struct RowMadArgs {
   const float* x;
   int64_t ld;          // row stride of x in samples
   int32_t N;           // row length
-  int32_t nblocks;     // row stride of med / mad
+  int32_t nblocks;     // blocks of the row (ceil(N / 64)), all written
+  int32_t ldm;         // row stride of med / mad in blocks (>= nblocks)
   int32_t rows;
-  const int32_t* med;  // [rows][nblocks]
-  int32_t* mad;        // [rows][nblocks], overwritten
+  const int32_t* med;  // [rows][ldm]: the row's first block first
+  int32_t* mad;        // [rows][ldm], first nblocks of each row overwritten
 };
 
 // Per-width re-normalisation: for every row and width w = 2^j the lower

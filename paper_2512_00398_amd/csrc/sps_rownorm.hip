@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_row_mad(RowMadArgs a) {
   __shared__ RowShared S;
   const int row = blockIdx.x;
   const float* x = a.x + (int64_t)row * a.ld;
-  const int32_t* m = a.med + (int64_t)row * a.nblocks;
+  const int32_t* m = a.med + (int64_t)row * a.ldm;
   const int n = a.N;
   const uint32_t rho = (uint32_t)((n - 1) / 2);
   constexpr int kHalf = kBins / 2;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_row_mad(RowMadArgs a) {
   if (!dwin)
     d = select_rank([&](int i) { const int v = resid(x, m, i) - c; return (uint32_t)(v < 0 ? -v : v); }, n, rho, 0u,
                     S);
-  int32_t* out = a.mad + (int64_t)row * a.nblocks;
+  int32_t* out = a.mad + (int64_t)row * a.ldm;
   for (int k = threadIdx.x; k < a.nblocks; k += kThreads) out[k] = (int32_t)d;
 }
 

@@ -19,24 +19,30 @@ def sps():
     return m
 
 
-def run_stream(x, gulp, max_width, L, theta, restore_after=None, detect_seg=0, stats_seg=0):
+def run_stream(x, gulp, max_width, L, theta, restore_after=None, detect_seg=0, stats_seg=0, norm=0, graph=False):
     import torch
     m = sps()
     ndm, total = x.shape
     assert total % gulp == 0
-    print("stream case ndm=%d total=%d gulp=%d w=%d L=%d restore=%s" % (ndm, total, gulp, max_width, L,
-                                                                       restore_after), flush=True)
+    print("stream case ndm=%d total=%d gulp=%d w=%d L=%d restore=%s norm=%d graph=%s" % (
+        ndm, total, gulp, max_width, L, restore_after, norm, graph), flush=True)
     parts = []
     with m.Plan(ndm, gulp, max_width, L, theta) as plan:
         if detect_seg:
             plan.set(m.ATTR_DETECT_SEG, detect_seg)
         if stats_seg:
             plan.set(m.ATTR_STATS_SEG, stats_seg)
+        if norm:
+            plan.set(m.ATTR_NORM, norm)
         cands, ncand = plan.alloc_cands()
         st = m.Stream(plan)
+        buf = torch.empty((ndm, gulp), dtype=torch.float32, device="cuda")
         for g in range(total // gulp):
             xd = torch.from_numpy(np.ascontiguousarray(x[:, g * gulp:(g + 1) * gulp])).cuda()
-            off = st.push(xd, cands, ncand)
+            if graph:  # replays read one fixed buffer
+                buf.copy_(xd)
+                xd = buf
+            off = st.push(xd, cands, ncand, graph=graph)
             torch.cuda.synchronize()
             assert off == g * gulp
             c = m.cands_to_numpy(cands, ncand, plan.max_cands)
@@ -111,6 +117,66 @@ def test_stream_workload_rows_full_length():
     sel = np.isin(got["dm_idx"], rows)
     assert compare_cands(got[sel], ref, b.snr_thresh, "c3-rows") == 0
     assert exact_equal(got[sel], ref)
+
+
+def gulp_scaled_block(seed, ndm, gulp, ngulps, w, L, factors):
+    # every gulp's samples multiplied by its own integer factor: the noise
+    # level changes from gulp to gulp, so one scale per gulp differs from
+    # the block scale and from one scale for the whole row
+    b = synth.Block(ndm=ndm, nsamp=gulp * ngulps, max_width=w, baseline_len=L, seed=seed, n_pulses=10,
+                    pulse_width=(1, min(w, 256)), pulse_snr=(8.0, 30.0), straddle_period=gulp)
+    x = synth.generate(b).astype(np.float64)
+    for g in range(ngulps):
+        x[:, g * gulp:(g + 1) * gulp] *= factors[g % len(factors)]
+    return x.astype(np.float32)
+
+
+ROW_SCALE_CASES = [
+    dict(name="short-gulps", ndm=5, gulp=2048, ngulps=6, w=256, L=3000, theta=5.0, factors=(1, 3, 2)),
+    dict(name="gulp=64", ndm=3, gulp=64, ngulps=40, w=128, L=200, theta=4.0, factors=(1, 2)),
+    dict(name="long-gulps", ndm=6, gulp=16384, ngulps=4, w=4096, L=4096, theta=5.5, factors=(2, 1, 4, 1)),
+]
+
+
+@pytest.mark.parametrize("case", ROW_SCALE_CASES, ids=[c["name"] for c in ROW_SCALE_CASES])
+def test_stream_row_scale_per_gulp(case):
+    # SPS_ATTR_NORM = 1 in a stream: one row scale per gulp (the oracle's
+    # reading 10 with the gulp as the chunk), eager, after a checkpoint and
+    # from captured graphs
+    x = gulp_scaled_block(1200 + len(case["name"]), case["ndm"], case["gulp"], case["ngulps"], case["w"], case["L"],
+                          case["factors"])
+    g = case["gulp"]
+    gulps = [x[:, k * g:(k + 1) * g] for k in range(case["ngulps"])]
+    ref = oracle.search_stream(gulps, case["w"], case["L"], case["theta"], row_norm=True)
+    got = run_stream(x, g, case["w"], case["L"], case["theta"], norm=1)
+    assert compare_cands(got, ref, case["theta"], case["name"]) == 0
+    assert exact_equal(got, ref)
+    assert ref.size > 0
+    assert not exact_equal(ref, oracle.search(x, case["w"], case["L"], case["theta"], row_norm=True))
+    restored = run_stream(x, g, case["w"], case["L"], case["theta"], norm=1, restore_after=case["ngulps"] // 2)
+    assert exact_equal(restored, ref)
+    graphed = run_stream(x, g, case["w"], case["L"], case["theta"], norm=1, graph=True)
+    assert exact_equal(graphed, ref)
+
+
+def test_stream_scale_attribute_checked_at_push():
+    import torch
+    m = sps()
+    with m.Plan(2, 4096, 64, 1000, 5.0) as p:
+        p.set(m.ATTR_NORM, 1)
+        st = m.Stream(p)
+        c, n = p.alloc_cands()
+        x = torch.zeros((2, 4096), dtype=torch.float32, device="cuda")
+        st.push(x, c, n)
+        p.set(m.ATTR_NORM, 2)  # the per-width scale needs the whole filtered series
+        with pytest.raises(m.SpsError):
+            st.push(x, c, n)
+        with pytest.raises(m.SpsError):
+            st.push(x, c, n, graph=True)
+        p.set(m.ATTR_NORM, 0)
+        st.push(x, c, n)
+        torch.cuda.synchronize()
+        st.close()
 
 
 def test_graph_gulp_step_matches_eager_every_replay():
@@ -233,12 +299,17 @@ def test_batch_push_equals_stream_push_and_oracle():
     # on its concatenated observation.
     import torch
     m = sps()
-    shapes = [(6, 4096, 512, 3000, 5.0, 3), (3, 8192, 4096, 5000, 5.5, 3), (9, 2048, 64, 700, 4.5, 3)]
+    shapes = [(6, 4096, 512, 3000, 5.0, 3), (3, 8192, 4096, 5000, 5.5, 3), (9, 2048, 64, 700, 4.5, 3),
+              (4, 2048, 256, 1500, 5.0, 3)]
+    norms = [0, 0, 0, 1]  # the last stream takes one row scale per gulp
     blocks = [synth.Block(ndm=nd, nsamp=g * ng, max_width=w, baseline_len=L, snr_thresh=th, seed=810 + k, n_pulses=6,
                           pulse_width=(1, min(w, 256)), pulse_snr=(6.0, 25.0), straddle_period=g)
               for k, (nd, g, w, L, th, ng) in enumerate(shapes)]
     xs = [synth.generate(b) for b in blocks]
+    xs[3] = gulp_scaled_block(833, 4, 2048, 3, 256, 1500, (1, 3, 2))
     plans = [m.Plan(nd, g, w, L, th) for (nd, g, w, L, th, _) in shapes]
+    for p, nrm in zip(plans, norms):
+        p.set(m.ATTR_NORM, nrm)
     streams = [m.Stream(p) for p in plans]
     bufs = [p.alloc_cands() for p in plans]
     parts = [[] for _ in shapes]
@@ -261,9 +332,9 @@ def test_batch_push_equals_stream_push_and_oracle():
         parts[i].append(_globalise(m.cands_to_numpy(c, n, plans[i].max_cands), end))
         got = oracle.sort_cands(np.concatenate(parts[i]))
         nd, g, w, L, th, ng = shapes[i]
-        alone = run_stream(xs[i], g, w, L, th)
+        alone = run_stream(xs[i], g, w, L, th, norm=norms[i])
         assert exact_equal(got, alone), i
-        ref = oracle.search(xs[i], w, L, th)
+        ref = oracle.search_stream([xs[i][:, k * g:(k + 1) * g] for k in range(ng)], w, L, th, row_norm=bool(norms[i]))
         assert compare_cands(got, ref, th, "batch push %d" % i) == 0 and exact_equal(got, ref), i
         st.close()
     for p in plans:
