@@ -47,7 +47,7 @@ MEASURED_TRAFFIC = {
     # profiles/dedisp_1024ch_1024dm_2p18.md
     "detect": ("e67eec6696954a69", (2237782 * 2 + 170188) * 1024),
     "block_stats": ("1d6a769e771e8b3c", (4349769 * 2 + 137136) * 1024),
-    "dedisp": ("a0a762ea61972dd1", (3436542 * 2 + 1048576) * 1024),
+    "dedisp": ("07ac2551669d5aea", (3431724 * 2 + 1048576) * 1024),
 }
 
 

@@ -120,6 +120,8 @@ class GulpRecord:
     submitted: float          # host seconds when enqueued
     done: Optional[float] = None
     ncand: Optional[int] = None
+    started: Optional[float] = None   # the device reached the gulp (its stream's event)
+    noticed: Optional[float] = None   # the host saw the completion (poll)
 
     @property
     def latency(self) -> float:
@@ -137,13 +139,33 @@ class Report:
     def latencies(self) -> np.ndarray:
         return np.array([r.latency for r in self.records], dtype=np.float64)
 
+    def breakdown(self) -> Optional[dict]:
+        """p50/p99 (ms) of each part of a gulp's life, where the executor timed it:
+        host_wait (arrival to submission: admission, free slot, scheduling loop),
+        device_queue (submission to its stream reaching it), search (on the
+        device), notice (completion to the host seeing it, the polling delay;
+        after the latency's end, but a slot stays busy until then)."""
+        recs = [r for r in self.records if r.started is not None and r.noticed is not None]
+        if not recs:
+            return None
+        parts = {"host_wait": [r.submitted - r.arrival for r in recs],
+                 "device_queue": [max(0.0, r.started - r.submitted) for r in recs],
+                 "search": [r.done - r.started for r in recs],
+                 "notice": [max(0.0, r.noticed - r.done) for r in recs]}
+        return {k: {"p50_ms": float(np.percentile(v, 50) * 1e3), "p99_ms": float(np.percentile(v, 99) * 1e3)}
+                for k, v in parts.items()}
+
     def summary(self) -> dict:
         lat = self.latencies()
-        return {"gulps": len(self.records), "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
-                "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
-                "max_ms": float(lat.max() * 1e3) if lat.size else None, "wall_s": self.wall,
-                "samples_per_s": self.samples / self.wall if self.wall > 0 else None,
-                "max_admitted_bytes": self.max_concurrent_bytes, "max_inflight": self.max_inflight}
+        out = {"gulps": len(self.records), "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+               "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+               "max_ms": float(lat.max() * 1e3) if lat.size else None, "wall_s": self.wall,
+               "samples_per_s": self.samples / self.wall if self.wall > 0 else None,
+               "max_admitted_bytes": self.max_concurrent_bytes, "max_inflight": self.max_inflight}
+        bd = self.breakdown()
+        if bd is not None:
+            out["breakdown"] = bd
+        return out
 
 
 def serve(specs: Sequence[BeamSpec], arrivals: Sequence[Arrival], executor, budget: int, compress: float = 1.0,
@@ -378,8 +400,10 @@ class GpuExecutor:
         for item in self.waiting:
             rec, began, ev, copied, host_n, x, cands, ncand, off = item
             if copied.query():
+                rec.noticed = time.perf_counter() - self.t0
                 rec.done = self._clock(ev)
-                self.intervals.append((rec.beam, self._clock(began), rec.done))
+                rec.started = self._clock(began)
+                self.intervals.append((rec.beam, rec.started, rec.done))
                 rec.ncand = int(host_n.item()) & 0xFFFFFFFF
                 if rec.ncand > self.cap:
                     raise sps.SpsError(sps.SPS_ERR_OVERFLOW, "gulp %d of beam %d" % (rec.k, rec.beam))

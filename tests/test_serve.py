@@ -45,6 +45,7 @@ class SimExecutor:
         assert rec.beam in self.open_beams
         now = self.clock() - self.t0
         start = max(now, self.free_at)
+        rec.started = start
         self.free_at = start + spec.ndm * spec.nsamp / self.rate
         self.q.append((self.free_at, rec))
         self.order[rec.beam].append(rec.k)
@@ -55,6 +56,7 @@ class SimExecutor:
         for t, r in self.q:
             if t <= now:
                 r.done = t
+                r.noticed = now
                 r.ncand = 0
         self.q = [(t, r) for t, r in self.q if t > now]
         return done
@@ -116,6 +118,28 @@ def test_serve_all_gulps_in_order_within_budget():
     assert s["gulps"] == 24 and s["p99_ms"] >= s["p50_ms"] > 0
 
 
+def test_latency_breakdown_adds_up():
+    # host wait + device queue + search is the latency; notice (the host
+    # seeing a completion) comes after it
+    clk = FakeClock()
+    specs = specs4()
+    arr = serve.poisson_arrivals(specs, 40.0, seed=5, gulps_per_beam=3)
+    ex = SimExecutor(clk, rate=2e9)
+    rep = serve.serve(specs, arr, ex, 1 << 40, compress=8.0, clock=clk, sleep=clk.sleep, slots=3)
+    for r in rep.records:
+        parts = (r.submitted - r.arrival) + (r.started - r.submitted) + (r.done - r.started)
+        assert abs(parts - r.latency) < 1e-9
+        assert r.submitted >= r.arrival and r.started >= r.submitted and r.noticed >= r.done
+    bd = rep.summary()["breakdown"]
+    assert set(bd) == {"host_wait", "device_queue", "search", "notice"}
+    for v in bd.values():
+        assert 0.0 <= v["p50_ms"] <= v["p99_ms"]
+    # a record the executor did not time leaves the breakdown out
+    rep.records[0].started = None
+    rep.records = rep.records[:1]
+    assert "breakdown" not in rep.summary()
+
+
 def test_serve_saturation_latency_grows():
     # Offered load above the device rate: the backlog, hence p99, grows with compression.
     sp = specs4()
@@ -172,6 +196,9 @@ def test_beam_in_mix_equals_alone_and_oracle():
           flush=True)
     assert rep.max_inflight >= 3
     assert beams >= 3
+    bd = rep.summary()["breakdown"]  # every part timed on the device and the host
+    print("latency parts", bd, flush=True)
+    assert bd["search"]["p50_ms"] > 0 and all(v["p50_ms"] >= 0 for v in bd.values())
     for b in range(3):
         print("beam %d alone" % b, flush=True)
         alone_ex = serve.GpuExecutor(source, nstreams=1, cand_cap=1 << 18, keep=True)
