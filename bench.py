@@ -450,7 +450,8 @@ def bench_serve(args):
     def run(compress, batch=True, **kw):
         arr = serve.poisson_arrivals(specs, rate, seed, **kw)
         ex = serve.GpuExecutor(source, nstreams=4, cand_cap=1 << 23, batch=batch)
-        rep = serve.serve(specs, arr, ex, budget, compress=compress, slots=args.serve_slots)
+        rep = serve.serve(specs, arr, ex, budget, compress=compress, slots=args.serve_slots,
+                          min_group=args.serve_min_group if batch else 1)
         s = rep.summary()
         s["compress"] = "inf" if compress == float("inf") else compress
         s["executor"] = "batched (sps_batch_push)" if batch else "one device stream per beam"
@@ -480,7 +481,8 @@ def bench_serve(args):
                                "theta=6, Poisson arrivals at %.1fx real time, budget %d B, %d gulps in flight" %
                                (cfg["name"], rate, budget, args.serve_slots),
                    "value_is": "saturation throughput (all arrivals at once), gulp = step",
-                   "executor": "continuous batching: gulps ready together share one launch per stage"},
+                   "executor": "continuous batching: gulps ready together share one launch per stage; under "
+                               "load ready gulps wait for %d free slots" % args.serve_min_group},
         "latency_literal_rate": literal,
         "latency_sweep": sweep,
         "saturation_per_beam_streams": per_beam,
@@ -502,6 +504,8 @@ def main():
     ap.add_argument("--serve-horizon", type=float, default=20.0,
                     help="seconds of literal-rate arrivals served in --config 5")
     ap.add_argument("--serve-slots", type=int, default=8, help="gulps in flight at most in --config 5")
+    ap.add_argument("--serve-min-group", type=int, default=4,
+                    help="--config 5, batched executor: under load, ready gulps wait for this many free slots")
     ap.add_argument("--cpu-rows", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain per-stage path")

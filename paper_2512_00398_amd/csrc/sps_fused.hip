@@ -62,6 +62,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const uint32_t* cnt = A.done + (task - D.offs[it]) / A.nseg;
         while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < A.done_target)
           __builtin_amdgcn_s_sleep(4);
+        // the thread that saw the count acquires the chains' releases; the
+        // barrier passes that on to the workgroup
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       s_task = task;
     }
@@ -69,7 +72,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int task = readfirst(s_task);
     __syncthreads();
     if (task >= D.total) break;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every wave's own view, after the barrier
     int it = 0;
     while (it + 1 < D.nitems && D.offs[it + 1] <= task) ++it;
     detect_body<NW, false>(D.items[it], task - D.offs[it]);

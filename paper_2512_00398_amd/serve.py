@@ -170,9 +170,12 @@ class Report:
 
 def serve(specs: Sequence[BeamSpec], arrivals: Sequence[Arrival], executor, budget: int, compress: float = 1.0,
           clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
-          slots: Optional[int] = None) -> Report:
+          slots: Optional[int] = None, min_group: int = 1) -> Report:
     """Run the arrivals through the executor; compress > 1 speeds the arrival clock up
-    (float('inf'): everything arrives at once); slots caps the gulps in flight."""
+    (float('inf'): everything arrives at once); slots caps the gulps in flight.
+    min_group > 1: while gulps are on the device, ready gulps wait until
+    min(min_group, ready) of them can go together (larger shared launches
+    under load; an idle device takes whatever is ready at once)."""
     left = collections.Counter(a.beam for a in arrivals)
     adm = Admission(budget)
     backlog: Dict[int, collections.deque] = collections.defaultdict(collections.deque)
@@ -195,6 +198,10 @@ def serve(specs: Sequence[BeamSpec], arrivals: Sequence[Arrival], executor, budg
     def dispatch() -> None:
         # every ready gulp that has a slot goes to the device now; an executor
         # that batches takes them together (gulps of different beams share a launch)
+        if min_group > 1 and inflight and ready:
+            free = len(ready) if slots is None else slots - len(inflight)
+            if free < min(min_group, len(ready)):
+                return
         group = []
         while ready and (slots is None or len(inflight) < slots):
             a, arrived = ready.popleft()

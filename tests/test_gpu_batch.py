@@ -173,6 +173,19 @@ def test_fused_launch_equals_per_stage_launches_and_oracle():
         got = run_batch(blocks, xs, tune=tune)
         for k, (g, r) in enumerate(zip(got, refs)):
             assert exact_equal(as_oracle(g), r), (tune, k)
+    # slow chains: rows too spread for the histogram take the exact select
+    # block by block, so their detection tasks wait far longer than the rest
+    rng = np.random.default_rng(77)
+    spread = np.round(rng.uniform(-4e6, 4e6, size=(6, 9000))).astype(np.float32)
+    spread[:, 4000:4003] += 8e6
+    sb = synth.Block(ndm=6, nsamp=9000, max_width=64, baseline_len=3000, snr_thresh=1.5, seed=1)
+    sref = oracle.search(spread, 64, 3000, 1.5)
+    for fused in (1, 0):
+        got = run_batch(blocks + [sb], xs + [torch.from_numpy(spread).cuda()], tune={m.ATTR_FUSED: fused})
+        assert exact_equal(as_oracle(got[-1]), sref), ("spread", fused)
+        for k, (g, r) in enumerate(zip(got[:-1], refs)):
+            assert exact_equal(as_oracle(g), r), ("with spread", fused, k)
+    assert sref.size > 0
     for fused in (1, 0):
         got = run_batch(blocks, xs, tune={m.ATTR_FUSED: fused, m.ATTR_WINDOW: 1})
         for k, (g, b, x) in enumerate(zip(got, blocks, xs)):

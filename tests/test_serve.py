@@ -140,6 +140,35 @@ def test_latency_breakdown_adds_up():
     assert "breakdown" not in rep.summary()
 
 
+def test_min_group_holds_gulps_for_shared_launches():
+    # under load, ready gulps wait for min_group free slots and then go
+    # together; with nothing on the device they go at once
+    class GroupExecutor(SimExecutor):
+        def __init__(self, *a, **kw):
+            super().__init__(*a, **kw)
+            self.groups = []
+
+        def submit_many(self, group):
+            self.groups.append(len(group))
+            for rec, spec in group:
+                self.submit(rec, spec)
+
+    clk = FakeClock()
+    sp = specs4()
+    arr = serve.poisson_arrivals(sp, 10.0, seed=3, gulps_per_beam=8)
+    out = {}
+    for mg in (1, 4):
+        ex = GroupExecutor(clk, rate=2e9)
+        rep = serve.serve(sp, arr, ex, 1 << 40, compress=float("inf"), clock=clk, sleep=clk.sleep, slots=8,
+                          min_group=mg)
+        assert len(rep.records) == len(arr) and rep.max_inflight <= 8
+        for b in range(len(sp)):
+            assert ex.order[b] == list(range(8))
+        out[mg] = ex.groups
+    assert max(out[1][1:]) < 4  # one slot frees at a time
+    assert min(out[4][:-1]) >= 4 and len(out[4]) < len(out[1])
+
+
 def test_serve_saturation_latency_grows():
     # Offered load above the device rate: the backlog, hence p99, grows with compression.
     sp = specs4()
