@@ -2045,7 +2045,6 @@ int sps_zero_dm(const uint8_t* d_in, int32_t nchan, int64_t nsamp, int32_t offse
   a.nsamp = nsamp;
   a.nchan = nchan;
   a.offset = offset;
-  a.aligned4 = (nsamp % 4 == 0) && (i0 % 4 == 0) && (o0 % 4 == 0);
   if (sps::launch_zero_dm(a, stream) != hipSuccess) return fail(SPS_ERR_HIP);
   return ok();
 }
@@ -2067,7 +2066,6 @@ int sps_chan_mask(const uint8_t* d_in, int32_t nchan, int64_t nsamp, int32_t k, 
   a.nsamp = nsamp;
   a.nchan = nchan;
   a.k = k;
-  a.aligned4 = (nsamp % 4 == 0) && (i0 % 4 == 0) && (o0 % 4 == 0);
   if (sps::launch_chan_mask(a, stream) != hipSuccess) return fail(SPS_ERR_HIP);
   return ok();
 }

@@ -123,7 +123,6 @@ struct ZeroDmArgs {
   int64_t nsamp;
   int32_t nchan;
   int32_t offset;
-  int32_t aligned4;  // 4-byte words: nsamp % 4 == 0 and both pointers 4-byte aligned
 };
 
 // Narrowband channel mask: in/out [nchan][nsamp] uint8 (may be the same
@@ -135,7 +134,6 @@ struct ChanMaskArgs {
   int64_t nsamp;
   int32_t nchan;
   int32_t k;
-  int32_t aligned4;  // 4-byte words: nsamp % 4 == 0 and both pointers 4-byte aligned
 };
 
 struct DetectArgs {

@@ -140,3 +140,54 @@ def test_chan_mask_then_zero_dm_full_size():
     torch.cuda.synchronize()
     assert np.array_equal(st.cpu().numpy()[:, 2].astype(bool), fl)
     assert np.array_equal(z.cpu().numpy(), ro.zero_dm(ref, 64))
+
+
+@pytest.mark.parametrize("nchan,nsamp", [(13, 1001), (5, 4096), (3, 7), (40, 257)])
+def test_rfi_on_buffers_at_odd_byte_offsets(nchan, nsamp):
+    # inputs and outputs that start 1 or 3 bytes into their buffer (every row,
+    # the first included, starts inside a 4-byte word), in and out of place
+    import torch
+    m = sps()
+    print("rfi odd offsets nchan=%d nsamp=%d" % (nchan, nsamp), flush=True)
+    rng = np.random.default_rng(nchan * 31 + nsamp)
+    fil = np.clip(np.rint(rng.normal(64, 6, size=(nchan, nsamp))), 0, 255).astype(np.uint8)
+    fil[::4] = np.clip(np.rint(rng.normal(90, 40, size=(len(range(0, nchan, 4)), nsamp))), 0, 255).astype(np.uint8)
+    fil[:, nsamp // 2] = 255
+    size = nchan * nsamp
+
+    def at(offset, src=None):
+        base = torch.full((size + 8,), 7, dtype=torch.uint8, device="cuda")
+        v = base[offset:offset + size].view(nchan, nsamp)
+        if src is not None:
+            v.copy_(torch.from_numpy(src))
+        return base, v
+
+    zref = ro.zero_dm(fil, 40)
+    mref, mu, sg, fl = ro.channel_mask(fil, 2)
+    for oi, oo in ((1, 3), (3, 1), (1, 0), (0, 3)):
+        bi, xi = at(oi, fil)
+        bo, xo = at(oo)
+        m.zero_dm(xi, 40, out=xo)
+        torch.cuda.synchronize()
+        assert np.array_equal(xo.cpu().numpy(), zref), (oi, oo)
+        assert np.array_equal(xi.cpu().numpy(), fil), (oi, oo)  # input untouched
+        guard = bo.cpu().numpy()
+        assert (guard[:oo] == 7).all() and (guard[oo + size:] == 7).all(), (oi, oo)  # nothing past the ends
+        bo, xo = at(oo)
+        out, st = m.chan_mask(xi, 2, out=xo)
+        torch.cuda.synchronize()
+        assert np.array_equal(xo.cpu().numpy(), mref), ("mask", oi, oo)
+        assert np.array_equal(st.cpu().numpy()[:, 0], mu) and np.array_equal(st.cpu().numpy()[:, 1], sg)
+        guard = bo.cpu().numpy()
+        assert (guard[:oo] == 7).all() and (guard[oo + size:] == 7).all(), ("mask", oi, oo)
+    for off in (1, 3):
+        bi, xi = at(off, fil)
+        m.zero_dm(xi, 40, out=xi)  # in place
+        torch.cuda.synchronize()
+        assert np.array_equal(xi.cpu().numpy(), zref), ("in place", off)
+        guard = bi.cpu().numpy()
+        assert (guard[:off] == 7).all() and (guard[off + size:] == 7).all(), ("in place", off)
+        bi, xi = at(off, fil)
+        m.chan_mask(xi, 2, out=xi)
+        torch.cuda.synchronize()
+        assert np.array_equal(xi.cpu().numpy(), mref), ("mask in place", off)
