@@ -45,9 +45,9 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md,
     # profiles/dedisp_1024ch_1024dm_2p18.md
-    "detect": ("e67eec6696954a69", (2237782 * 2 + 170188) * 1024),
-    "block_stats": ("1d6a769e771e8b3c", (4349769 * 2 + 137136) * 1024),
-    "dedisp": ("07ac2551669d5aea", (3431724 * 2 + 1048576) * 1024),
+    "detect": ("68d5c2488a9777eb", (2237782 * 2 + 170188) * 1024),
+    "block_stats": ("14731cac944ef84e", (4349769 * 2 + 137136) * 1024),
+    "dedisp": ("1f8cc33eb856bd29", (3431724 * 2 + 1048576) * 1024),
 }
 
 
@@ -56,8 +56,8 @@ MEASURED_TRAFFIC = {
 VALU_ISSUE_PER_S = 256 * 2.4e9
 MEASURED_VALU = {
     # kernel: (sources hash, SQ_INSTS_VALU per launch); profiles/kernels_c2_1024x2p20.md
-    "detect": ("e67eec6696954a69", 3.311e9),
-    "block_stats": ("1d6a769e771e8b3c", 1.875e9),
+    "detect": ("68d5c2488a9777eb", 3.311e9),
+    "block_stats": ("14731cac944ef84e", 1.875e9),
 }
 
 
