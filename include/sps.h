@@ -328,8 +328,11 @@ int sps_batch_create(sps_batch** out);
  *   different shapes and parameters. d_cands / d_ncand are host arrays of n
  *   device pointers (capacity: the stream's plan SPS_ATTR_MAX_CANDS). A
  *   stream may appear once per call (its next gulp needs this one's carry);
- *   it must not be used concurrently elsewhere. Uses the context's
- *   SPS_ATTR_HIST_BINS; plan timing is not recorded. Asynchronous, except
+ *   it must not be used concurrently elsewhere. Each stream keeps its own
+ *   plan's scale (one row scale per gulp with SPS_ATTR_NORM = 1); a stream
+ *   whose plan has since been set to a centred window or the per-width
+ *   scale is refused. Uses the context's SPS_ATTR_HIST_BINS; plan timing is
+ *   not recorded. Asynchronous, except
  *   that a call needing larger tables than any earlier one first waits for
  *   the context's earlier work. SPS_OK, SPS_ERR_INVALID_ARG (nothing
  *   enqueued), SPS_ERR_DOMAIN (plan validation), SPS_ERR_OOM, SPS_ERR_HIP.
