@@ -32,8 +32,9 @@ ALU_PAIR_ADD_PEAK_TOPS = 2 * ALU_INT32_PEAK_TOPS
 # HBM bytes per launch on the default workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a
 # 1 GiB device copy (fetch x 2.000, write x 1.000); the command lines and raw
-# figures are in profiles/. A figure is reported only while the sources it
-# was measured on are unchanged (hash of the files below), else null.
+# figures are in profiles/. A figure is reported only while the code it was
+# measured on is unchanged (hash of the files below without their comments),
+# else null.
 _CSRC = "paper_2512_00398_amd/csrc/"
 KERNEL_SOURCES = {
     "detect": [_CSRC + "sps_detect.hip", _CSRC + "sps_detect_body.h", _CSRC + "sps_runs.h", _CSRC + "sps_wave.h",
@@ -45,9 +46,9 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # kernel: (sources hash, bytes per launch); profiles/kernels_c2_1024x2p20.md,
     # profiles/dedisp_1024ch_1024dm_2p18.md
-    "detect": ("68d5c2488a9777eb", (2237782 * 2 + 170188) * 1024),
-    "block_stats": ("14731cac944ef84e", (4349769 * 2 + 137136) * 1024),
-    "dedisp": ("1f8cc33eb856bd29", (3431724 * 2 + 1048576) * 1024),
+    "detect": ("28cb64f53eaf4840", (2237782 * 2 + 170188) * 1024),
+    "block_stats": ("83db0f9652526326", (4349769 * 2 + 137136) * 1024),
+    "dedisp": ("ba24418b892897af", (3431724 * 2 + 1048576) * 1024),
 }
 
 
@@ -56,8 +57,8 @@ MEASURED_TRAFFIC = {
 VALU_ISSUE_PER_S = 256 * 2.4e9
 MEASURED_VALU = {
     # kernel: (sources hash, SQ_INSTS_VALU per launch); profiles/kernels_c2_1024x2p20.md
-    "detect": ("68d5c2488a9777eb", 3.311e9),
-    "block_stats": ("14731cac944ef84e", 1.875e9),
+    "detect": ("28cb64f53eaf4840", 3.311e9),
+    "block_stats": ("83db0f9652526326", 1.875e9),
 }
 
 
@@ -69,11 +70,17 @@ def measured_issue(kernel: str):
 
 
 def sources_hash(kernel: str) -> str:
+    """Hash of the kernel's sources with comments and whitespace removed (a
+    comment cannot change the code the counters were taken on)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[kernel]:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), "r", encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
