@@ -194,3 +194,45 @@ def test_fused_launch_equals_per_stage_launches_and_oracle():
     with pytest.raises(m.SpsError):
         with m.Batch() as b:
             b.set(m.ATTR_FUSED, 2)
+
+
+def test_fused_equals_per_stage_on_random_batches():
+    # Seeded random batches of uneven blocks (rows, lengths, widths, windows,
+    # thresholds, chain and segment lengths): the one-launch form must give
+    # bit-identical results to one launch per stage, and small items the
+    # oracle's.
+    import torch
+    m = sps()
+    rng = np.random.default_rng(2026)
+    checked = 0
+    for trial in range(8):
+        nitems = int(rng.integers(1, 7))
+        blocks = []
+        for k in range(nitems):
+            w = 1 << int(rng.integers(0, 13))
+            n = int(rng.integers(64, 40000))
+            blocks.append(synth.Block(ndm=int(rng.integers(1, 12)), nsamp=n, max_width=w,
+                                      baseline_len=int(rng.integers(1, 20000)), snr_thresh=float(rng.uniform(3.0, 6.0)),
+                                      seed=3000 + 10 * trial + k, n_pulses=3, pulse_width=(1, max(1, min(w, 128))),
+                                      pulse_snr=(6.0, 20.0)))
+        xs = [torch.from_numpy(synth.generate(b)).cuda() for b in blocks]
+        tune = {}
+        if rng.random() < 0.5:
+            tune[m.ATTR_STATS_SEG] = int(rng.choice([1, 16, 64, 500]))
+        if rng.random() < 0.5:
+            tune[m.ATTR_DETECT_SEG] = int(rng.choice([1024, 3072, 8192]))
+        if rng.random() < 0.3:
+            tune[m.ATTR_WINDOW] = 1
+        print("random batch %d: %d items %s tune=%s" % (trial, nitems, [(b.ndm, b.nsamp, b.max_width) for b in blocks],
+                                                      tune), flush=True)
+        fused = run_batch(blocks, xs, tune={**tune, m.ATTR_FUSED: 1})
+        staged = run_batch(blocks, xs, tune={**tune, m.ATTR_FUSED: 0})
+        for k in range(nitems):
+            assert exact_equal(as_oracle(fused[k]), as_oracle(staged[k])), (trial, k)
+            b = blocks[k]
+            if b.ndm * b.nsamp <= 60000:
+                ref = oracle.search(xs[k].cpu().numpy(), b.max_width, b.baseline_len, b.snr_thresh,
+                                    centered=tune.get(m.ATTR_WINDOW, 0) == 1)
+                assert exact_equal(as_oracle(fused[k]), ref), (trial, k)
+                checked += 1
+    assert checked > 0
