@@ -339,3 +339,28 @@ def test_batch_push_equals_stream_push_and_oracle():
         st.close()
     for p in plans:
         p.close()
+
+
+def test_streams_on_random_shapes_equal_oracle():
+    # Seeded random streams (gulp lengths that are multiples of 64, widths,
+    # windows, thresholds, the block scale or one row scale per gulp, noise
+    # changing from gulp to gulp): every stream equals the oracle's reading of
+    # its concatenated gulps.
+    rng = np.random.default_rng(909)
+    for trial in range(8):
+        gulp = 64 * int(rng.integers(1, 64))
+        ng = int(rng.integers(2, 7))
+        w = 1 << int(rng.integers(0, 11))
+        L = int(rng.integers(1, 6000))
+        th = float(rng.uniform(3.5, 6.0))
+        norm = int(rng.integers(0, 2))
+        ndm = int(rng.integers(1, 6))
+        factors = tuple(int(f) for f in rng.integers(1, 4, size=3))
+        x = gulp_scaled_block(4000 + trial, ndm, gulp, ng, w, L, factors)
+        print("random stream %d: ndm=%d gulp=%d x%d w=%d L=%d norm=%d" % (trial, ndm, gulp, ng, w, L, norm),
+              flush=True)
+        got = run_stream(x, gulp, w, L, th, norm=norm, graph=bool(trial % 2))
+        ref = oracle.search_stream([x[:, k * gulp:(k + 1) * gulp] for k in range(ng)], w, L, th,
+                                   row_norm=bool(norm))
+        assert compare_cands(got, ref, th, "random stream %d" % trial) == 0
+        assert exact_equal(got, ref), trial
