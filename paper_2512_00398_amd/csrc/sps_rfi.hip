@@ -109,6 +109,124 @@ __global__ __launch_bounds__(64 * kZdWaves) void k_zero_dm(ZeroDmArgs a) {
   }
 }
 
+// Read-once form (up to 1024 channels, input and output at the same
+// alignment mod 4, under 4 GiB): a workgroup covers 252 samples and each wave
+// keeps the words of its channels (f = wave, wave + 16, ...) in registers
+// from the sums to the rewrite, so the filterbank is read once and written
+// once, and every load of a wave is issued before the first is needed. Lane l
+// of a wave owns word l of the tile, tile bytes 4l - lead .. 4l - lead + 3,
+// where lead puts the word on a 4-byte boundary of the row (the same one in
+// input and output); 64 words always cover the 252 samples. lead is the same
+// for all of a wave's channels: their rows start 16 * nsamp bytes apart and
+// the tile start is a multiple of 4. Addresses are one scalar base per wave
+// plus 32-bit offsets. Bytes outside the tile are kept out of the sums and
+// never written; the aligned word that holds a wanted byte lies in the same
+// page, so every read stays in mapped memory.
+constexpr int kZrSpan = 252;  // samples per workgroup (a multiple of 4)
+
+template <int CPW>
+__global__ __launch_bounds__(64 * kZdWaves) void k_zero_dm_reg(ZeroDmArgs a, int per_xcd) {
+  __shared__ uint32_t part[kZdWaves][kZrSpan + 8];  // tile sample j at index j + 4
+  __shared__ int zs[kZrSpan + 8];
+  // XCD-aware order: workgroup b runs on XCD b % 8, which takes a contiguous
+  // range of tiles, so neighbouring tiles (sharing a cache line in every
+  // row) run together under one L2
+  const int64_t tile = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (tile * kZrSpan >= a.nsamp) return;  // whole workgroup, before any barrier
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t t0 = tile * kZrSpan;
+  const int tv = (int)min<int64_t>(kZrSpan, a.nsamp - t0);  // samples of this tile, >= 1
+  const uint32_t S = (uint32_t)(kZdWaves * a.nsamp);        // bytes between a wave's channels
+  // the wave's first channel (channel 0 for a wave with none: it only reads it)
+  const int wrow = wave < a.nchan ? wave : 0;
+  const uint8_t* in0 = a.in + (int64_t)wrow * a.nsamp + t0 - 4;  // 4 bytes before the tile
+  uint8_t* out0 = a.out + (int64_t)wrow * a.nsamp + t0 - 4;
+  const int lead = (int)(reinterpret_cast<uintptr_t>(out0 + 4) & 3u);
+  const int j0 = 4 * lane - lead;                        // the word: tile bytes j0 .. j0 + 3
+  const int blo = max(0, -j0), bhi = min(4, tv - j0);  // the tile's bytes of the word: [blo, bhi)
+  const bool any = bhi > blo;
+  const uint32_t keep = !any ? 0u
+                             : ((bhi >= 4 ? 0xFFFFFFFFu : ((1u << (8 * bhi)) - 1u)) & ~((1u << (8 * blo)) - 1u));
+  const uint32_t vo = (uint32_t)(4 + j0);  // >= 1
+  // a lane with no byte of the tile reads the word of tile byte 0 and keeps nothing
+  const uint32_t vl = any ? vo : (uint32_t)(4 - lead);
+  // Raw buffers over the wave's rows (descriptor word 3 as for every gfx9
+  // raw buffer: 32-bit data format; no range limit below 2^32): the lane
+  // offset in a VGPR, the channel's offset i * S in a scalar register.
+  const __amdgpu_buffer_rsrc_t rin = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(in0), 0, -1, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc(out0, 0, -1, 0x00020000);
+  const int nv = min(CPW, (a.nchan - wave + kZdWaves - 1) / kZdWaves);  // the wave's channels, >= 0
+  uint32_t v[CPW];
+  uint32_t slo = 0, shi = 0;  // samples 0 and 2, 1 and 3 of the word as 16-bit sums (CPW * 255 < 2^16)
+  // A channel past nchan reads the wave's first one again (no branch or mask
+  // between the loads); its copies are taken out of the sums after the loop.
+#pragma unroll
+  for (int i = 0; i < CPW; ++i) {
+    const int so = i < nv ? (int)((uint32_t)i * S) : 0;
+    v[i] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rin, (int)vl, so, 0) & keep;
+    slo += __builtin_amdgcn_perm(0u, v[i], 0x0c020c00u);
+    shi += __builtin_amdgcn_perm(0u, v[i], 0x0c030c01u);
+  }
+  if (nv < CPW) {  // each 16-bit lane holds those copies, so no borrow crosses lanes
+    slo -= (uint32_t)(CPW - nv) * __builtin_amdgcn_perm(0u, v[0], 0x0c020c00u);
+    shi -= (uint32_t)(CPW - nv) * __builtin_amdgcn_perm(0u, v[0], 0x0c030c01u);
+  }
+  uint32_t* pw = &part[wave][4 + j0];  // j0 + 4 >= 1
+  pw[0] = slo & 0xFFFFu;
+  pw[1] = shi & 0xFFFFu;
+  pw[2] = slo >> 16;
+  pw[3] = shi >> 16;
+  __syncthreads();
+  // sums <= 255 * 1024: 2 * sum + nchan fits 32 bits
+  if ((int)threadIdx.x < tv) {
+    uint32_t sum = 0;
+#pragma unroll
+    for (int w = 0; w < kZdWaves; ++w) sum += part[w][4 + threadIdx.x];
+    const uint32_t c = (uint32_t)a.nchan;
+    zs[4 + threadIdx.x] = (int)((2u * sum + c) / (2u * c)) - a.offset;
+  }
+  __syncthreads();
+  // levels of the word's four samples as two 16-bit pairs (bytes 0/2, 1/3);
+  // in - level lies in [-255, 510], which 16-bit lanes hold
+  typedef short short2_t __attribute__((ext_vector_type(2)));
+  int z[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) z[q] = (q >= blo && q < bhi) ? zs[4 + j0 + q] : 0;
+  const short2_t zl = {(short)z[0], (short)z[2]}, zh = {(short)z[1], (short)z[3]};
+  const short2_t lo0 = {0, 0}, hi255 = {255, 255};
+  const bool whole = blo == 0 && bhi == 4;
+  // the channel stride and count, opaque here: otherwise the compiler keeps
+  // the loads' 64 channel offsets and conditions alive for the stores and
+  // spills them
+  int Sr = (int)S, nvr = nv;
+  asm volatile("" : "+s"(Sr), "+s"(nvr));
+#pragma unroll
+  for (int i = 0; i < CPW; ++i) {
+    // the word opaque too: the byte pairs formed for the sums are not kept
+    // alive until here (that would be two registers per channel)
+    uint32_t x = v[i];
+    asm volatile("" : "+v"(x));
+    short2_t l = __builtin_bit_cast(short2_t, __builtin_amdgcn_perm(0u, x, 0x0c020c00u)) - zl;
+    short2_t h = __builtin_bit_cast(short2_t, __builtin_amdgcn_perm(0u, x, 0x0c030c01u)) - zh;
+    l = __builtin_elementwise_min(__builtin_elementwise_max(l, lo0), hi255);
+    h = __builtin_elementwise_min(__builtin_elementwise_max(h, lo0), hi255);
+    // bytes 0 and 2 of l and of h, interleaved back into sample order
+    const uint32_t o = __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, h), __builtin_bit_cast(uint32_t, l),
+                                             0x06020400u);
+    if (i < nvr) {
+      if (whole) {
+        __builtin_amdgcn_raw_buffer_store_b32(o, rout, (int)vo, (int)((uint32_t)i * (uint32_t)Sr), 0);
+      } else if (any) {  // a word at the tile's ends: only the tile's own bytes
+        uint8_t* ob = out0 + (vo + (uint32_t)i * (uint32_t)Sr);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q >= blo && q < bhi) ob[q] = (uint8_t)(o >> (8 * q));
+      }
+    }
+  }
+}
+
 // ---- narrowband: per-channel statistics, flags, replacement -----------------
 // Exact order statistics of bytes from a 256-bin histogram H with n values:
 // the lower median (rank (n-1)/2) and the lower MAD about it, found by
@@ -132,14 +250,22 @@ __device__ void hist_median_mad(const uint32_t* H, uint32_t n, int& mu, int& mad
   mad = d;
 }
 
-// One workgroup per channel: byte histogram of the row (one sub-histogram
-// per wave against same-bin contention), then its median and MAD.
+// One workgroup per channel: byte histogram of the row, then its median and
+// MAD. Noise bytes crowd into a few bins, and LDS atomics of one instruction
+// on one address are serialised: each wave keeps 16 sub-histograms (lane
+// l counts into copy l % 16, so at most 4 lanes share an address), 257 words
+// apart so that the copies of a bin fall in different banks. 64 x 257 words
+// (66 KB): two workgroups per CU.
+constexpr int kCsCopies = 16;
+constexpr int kCsStride = 257;
+
 __global__ __launch_bounds__(256) void k_chan_stats(ChanMaskArgs a) {
-  __shared__ uint32_t h[4][256];
-  const int tid = threadIdx.x, wave = tid >> 6;
+  __shared__ uint32_t h[4 * kCsCopies * kCsStride];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int f = blockIdx.x;
-  for (int b = tid; b < 4 * 256; b += 256) (&h[0][0])[b] = 0;
+  for (int b = tid; b < 4 * kCsCopies * kCsStride; b += 256) h[b] = 0;
   __syncthreads();
+  uint32_t* mine = h + (wave * kCsCopies + (lane & (kCsCopies - 1))) * kCsStride;
   // The row read as the aligned 4-byte words that cover it, whatever its
   // alignment (rows of an odd length start anywhere in a word): bytes of a
   // word outside the row are skipped. A word holding one byte of the row
@@ -147,27 +273,46 @@ __global__ __launch_bounds__(256) void k_chan_stats(ChanMaskArgs a) {
   const uintptr_t start = reinterpret_cast<uintptr_t>(a.in + (int64_t)f * a.nsamp);
   const int lead = (int)(start & 3u);
   const uint32_t* words = reinterpret_cast<const uint32_t*>(start - (uintptr_t)lead);
-  const int64_t nw = (lead + a.nsamp + 3) >> 2;
   const int64_t last = lead + a.nsamp;  // one past the row's last byte, in word-byte units
-  for (int64_t k = tid; k < nw; k += 256) {
-    const uint32_t w = words[k];
-    const int64_t b0 = 4 * k;
-    if (b0 >= lead && b0 + 4 <= last) {
-      atomicAdd(&h[wave][w & 0xFFu], 1u);
-      atomicAdd(&h[wave][(w >> 8) & 0xFFu], 1u);
-      atomicAdd(&h[wave][(w >> 16) & 0xFFu], 1u);
-      atomicAdd(&h[wave][w >> 24], 1u);
-    } else {
-      for (int q = 0; q < 4; ++q)
-        if (b0 + q >= lead && b0 + q < last) atomicAdd(&h[wave][(w >> (8 * q)) & 0xFFu], 1u);
+  auto count4 = [&](uint32_t w) {
+    atomicAdd(&mine[w & 0xFFu], 1u);
+    atomicAdd(&mine[(w >> 8) & 0xFFu], 1u);
+    atomicAdd(&mine[(w >> 16) & 0xFFu], 1u);
+    atomicAdd(&mine[w >> 24], 1u);
+  };
+  // words wholly inside the row: k = kf .. kl; four loads in flight per thread
+  const int64_t kf = lead > 0 ? 1 : 0, kl = (last >> 2) - 1;
+  int64_t k = kf + tid;
+  for (; k + 768 <= kl; k += 1024) {
+    const uint32_t w0 = words[k], w1 = words[k + 256], w2 = words[k + 512], w3 = words[k + 768];
+    count4(w0);
+    count4(w1);
+    count4(w2);
+    count4(w3);
+  }
+  for (; k <= kl; k += 256) count4(words[k]);
+  // the words at the row's ends, byte by byte: only the row's bytes
+  if (tid < 2) {
+    const int64_t ke = tid == 0 ? 0 : (last >> 2);
+    // (the last word is thread 1's unless it is word 0 and thread 0's already)
+    const bool edge = tid == 0 ? lead > 0 : ((last & 3) != 0 && (ke != 0 || lead == 0));
+    if (edge) {
+      const uint32_t w = words[ke];
+      for (int q = 0; q < 4; ++q) {
+        const int64_t b = 4 * ke + q;
+        if (b >= lead && b < last) atomicAdd(&mine[(w >> (8 * q)) & 0xFFu], 1u);
+      }
     }
   }
   __syncthreads();
-  h[0][tid] += h[1][tid] + h[2][tid] + h[3][tid];
+  uint32_t t = 0;
+  for (int c = 0; c < 4 * kCsCopies; ++c) t += h[c * kCsStride + tid];
+  __syncthreads();
+  h[tid] = t;
   __syncthreads();
   if (tid == 0) {
     int mu, mad;
-    hist_median_mad(h[0], (uint32_t)a.nsamp, mu, mad);
+    hist_median_mad(h, (uint32_t)a.nsamp, mu, mad);
     a.stats[3 * (int64_t)f] = (uint8_t)mu;
     a.stats[3 * (int64_t)f + 1] = (uint8_t)mad;
   }
@@ -190,26 +335,59 @@ __global__ __launch_bounds__(256) void k_chan_flags(ChanMaskArgs a) {
 }
 
 // Flagged channels take their median; the others are copied (nothing to do
-// in place). Thread k writes the row's aligned output word k (the row read
-// as aligned words too, realigned); the one or two words at the row's ends
-// are written byte by byte, only the row's own bytes.
+// in place). A workgroup writes 1024 aligned output words of a row, four per
+// thread 256 words apart (the row read as aligned words too, realigned; all
+// four loads issued before the stores: a thread's words are its own, in
+// place as well); the one or two words at the row's ends are written byte by
+// byte, only the row's own bytes.
+constexpr int kApplyWords = 4;
+
 __global__ __launch_bounds__(256) void k_chan_apply(ChanMaskArgs a) {
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   for (int f = blockIdx.y; f < a.nchan; f += gridDim.y) {
     const bool flag = a.stats[3 * (int64_t)f + 2] != 0;
     if (!flag && a.in == a.out) continue;
     const int64_t row = (int64_t)f * a.nsamp;
     const int lead = (int)((reinterpret_cast<uintptr_t>(a.out + row)) & 3u);
-    const int64_t j0 = 4 * k - lead;
-    if (j0 >= a.nsamp || j0 + 4 <= 0) continue;
     const uint8_t mu = a.stats[3 * (int64_t)f];
-    if (j0 >= 0 && j0 + 4 <= a.nsamp) {
-      const uint32_t v = flag ? 0x01010101u * mu : load4(a.in + row + j0, 4);
-      *reinterpret_cast<uint32_t*>(a.out + row + j0) = v;
-    } else {
-      for (int q = 0; q < 4; ++q) {
-        const int64_t j = j0 + q;
-        if (j >= 0 && j < a.nsamp) a.out[row + j] = flag ? mu : a.in[row + j];
+    // input row at the output row's alignment (the usual case): its words
+    // are aligned too, one load each
+    const bool al = (int)((reinterpret_cast<uintptr_t>(a.in + row)) & 3u) == lead;
+    uint32_t v[kApplyWords];
+    int64_t j[kApplyWords];
+#pragma unroll
+    for (int u = 0; u < kApplyWords; ++u) {
+      j[u] = 4 * ((int64_t)blockIdx.x * (256 * kApplyWords) + u * 256 + threadIdx.x) - lead;
+      v[u] = 0x01010101u * mu;
+    }
+    // whole words of the row: j = jf, jf + 4, ..., jl
+    const int64_t jf = (4 - lead) & 3, jl = jf + 4 * ((a.nsamp - 4 - jf) >> 2);
+    if (!flag) {
+      if (al && jl >= jf) {
+        // every lane loads (a whole word of the row, clamped) and keeps what
+        // it needs: loads under a lane condition make the compiler wait for
+        // each before the next
+#pragma unroll
+        for (int u = 0; u < kApplyWords; ++u) {
+          const uint32_t w = *reinterpret_cast<const uint32_t*>(a.in + row + min(max(j[u], jf), jl));
+          v[u] = (j[u] >= 0 && j[u] + 4 <= a.nsamp) ? w : v[u];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kApplyWords; ++u)
+          if (j[u] >= 0 && j[u] + 4 <= a.nsamp) v[u] = load4(a.in + row + j[u], 4);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kApplyWords; ++u) {
+      const int64_t j0 = j[u];
+      if (j0 >= a.nsamp || j0 + 4 <= 0) continue;
+      if (j0 >= 0 && j0 + 4 <= a.nsamp) {
+        *reinterpret_cast<uint32_t*>(a.out + row + j0) = v[u];
+      } else {
+        for (int q = 0; q < 4; ++q) {
+          const int64_t jj = j0 + q;
+          if (jj >= 0 && jj < a.nsamp) a.out[row + jj] = flag ? mu : a.in[row + jj];
+        }
       }
     }
   }
@@ -221,14 +399,26 @@ hipError_t launch_chan_mask(const ChanMaskArgs& a, hipStream_t s) {
   if (a.nsamp <= 0 || a.nchan <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_chan_stats, dim3((unsigned)a.nchan), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_chan_flags, dim3(1), dim3(256), 0, s, a);
-  const unsigned gx = (unsigned)((a.nsamp / 4 + 2 + 255) / 256), gy = (unsigned)min(a.nchan, 65535);
+  // aligned output words of a row: at most nsamp / 4 + 2
+  const unsigned gx = (unsigned)((a.nsamp / 4 + 2 + 256 * kApplyWords - 1) / (256 * kApplyWords));
+  const unsigned gy = (unsigned)min(a.nchan, 65535);
   hipLaunchKernelGGL(k_chan_apply, dim3(gx, gy), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_zero_dm(const ZeroDmArgs& a, hipStream_t s) {
   if (a.nsamp <= 0 || a.nchan <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_dm, dim3((unsigned)((a.nsamp + kZdSpan - 1) / kZdSpan)), dim3(64 * kZdWaves), 0, s, a);
+  const dim3 t(64 * kZdWaves);
+  // the read-once kernel: same alignment mod 4 in and out, 32-bit offsets
+  // (every offset below nchan * nsamp + 4), at most 64 channels per wave
+  const bool same4 = ((reinterpret_cast<uintptr_t>(a.in) ^ reinterpret_cast<uintptr_t>(a.out)) & 3u) == 0;
+  const bool small = (int64_t)a.nchan * a.nsamp + 8 < ((int64_t)1 << 32);
+  const int per_xcd = (int)(((a.nsamp + kZrSpan - 1) / kZrSpan + 7) / 8);
+  const dim3 gr(8u * (unsigned)per_xcd);
+  if (same4 && small && a.nchan <= 4 * kZdWaves) hipLaunchKernelGGL(k_zero_dm_reg<4>, gr, t, 0, s, a, per_xcd);
+  else if (same4 && small && a.nchan <= 16 * kZdWaves) hipLaunchKernelGGL(k_zero_dm_reg<16>, gr, t, 0, s, a, per_xcd);
+  else if (same4 && small && a.nchan <= 64 * kZdWaves) hipLaunchKernelGGL(k_zero_dm_reg<64>, gr, t, 0, s, a, per_xcd);
+  else hipLaunchKernelGGL(k_zero_dm, dim3((unsigned)((a.nsamp + kZdSpan - 1) / kZdSpan)), t, 0, s, a);
   return hipGetLastError();
 }
 

@@ -28,7 +28,12 @@ def run(fil, offset, in_place=False):
 
 
 @pytest.mark.parametrize("nchan,nsamp,offset", [(1, 1, 0), (3, 7, 255), (64, 1000, 64), (100, 1003, 30),
-                                                (1000, 4096, 128), (7, 257, 1)])
+                                                (1000, 4096, 128), (7, 257, 1),
+                                                # the read-once kernel's channels per wave (4, 16, 64) at their
+                                                # limits, one 252-sample tile and its neighbours; over 1024
+                                                # channels the two-pass kernel
+                                                (65, 503, 10), (256, 252, 200), (257, 253, 0), (1024, 259, 64),
+                                                (1025, 300, 64), (16, 251, 3), (17, 505, 255)])
 def test_zero_dm_parity(nchan, nsamp, offset):
     print("zero-dm case nchan=%d nsamp=%d offset=%d" % (nchan, nsamp, offset), flush=True)
     sys.stdout.flush()
@@ -106,7 +111,10 @@ def run_mask(fil, k, in_place=False):
     return out.cpu().numpy(), st.cpu().numpy()
 
 
-@pytest.mark.parametrize("nchan,nsamp,k", [(1, 1, 0), (2, 5, 0), (64, 3000, 3), (37, 1001, 2), (300, 4096, 0)])
+@pytest.mark.parametrize("nchan,nsamp,k", [(1, 1, 0), (2, 5, 0), (64, 3000, 3), (37, 1001, 2), (300, 4096, 0),
+                                           # rows of 2 and 3 bytes (one partial word each), and rows long
+                                           # enough for the statistics' four-word steps with a tail
+                                           (5, 2, 0), (6, 3, 1), (9, 4097 * 4 + 3, 1)])
 def test_chan_mask_parity(nchan, nsamp, k):
     print("chan-mask case nchan=%d nsamp=%d k=%d" % (nchan, nsamp, k), flush=True)
     rng = np.random.default_rng(nchan + 3 * nsamp)
@@ -144,8 +152,10 @@ def test_chan_mask_then_zero_dm_full_size():
 
 @pytest.mark.parametrize("nchan,nsamp", [(13, 1001), (5, 4096), (3, 7), (40, 257)])
 def test_rfi_on_buffers_at_odd_byte_offsets(nchan, nsamp):
-    # inputs and outputs that start 1 or 3 bytes into their buffer (every row,
-    # the first included, starts inside a 4-byte word), in and out of place
+    # inputs and outputs that start 1, 2 or 3 bytes into their buffer (every
+    # row, the first included, starts inside a 4-byte word), in and out of
+    # place; at the same alignment mod 4 zero-DM takes its read-once kernel,
+    # otherwise the two-pass one
     import torch
     m = sps()
     print("rfi odd offsets nchan=%d nsamp=%d" % (nchan, nsamp), flush=True)
@@ -164,7 +174,7 @@ def test_rfi_on_buffers_at_odd_byte_offsets(nchan, nsamp):
 
     zref = ro.zero_dm(fil, 40)
     mref, mu, sg, fl = ro.channel_mask(fil, 2)
-    for oi, oo in ((1, 3), (3, 1), (1, 0), (0, 3)):
+    for oi, oo in ((1, 3), (3, 1), (1, 0), (0, 3), (1, 1), (3, 3), (2, 2)):
         bi, xi = at(oi, fil)
         bo, xo = at(oo)
         m.zero_dm(xi, 40, out=xo)
