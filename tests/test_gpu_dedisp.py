@@ -73,6 +73,25 @@ def test_wide_spread_uses_smaller_trial_groups():
     check(fil, tab, "wide-spread")
 
 
+@pytest.mark.parametrize("spread", [0, 1, 700, 1526, 3000, 7157, 7158, 7159])
+def test_trial_group_spread_edges(spread):
+    # The spread of the delays of 16 neighbouring trials in a channel decides
+    # the trials per workgroup: 16 up to 7158 samples (at 7158 the largest
+    # staged span, 2048 words), then fewer. Channels are offset from one
+    # another and the rows have an odd length, so the spans start at every
+    # byte alignment.
+    rng = np.random.default_rng(spread + 11)
+    nchan, ndm = 6, 37
+    ramp = np.round(np.linspace(0, spread, 16)).astype(np.int64)
+    tab = np.zeros((ndm, nchan), dtype=np.int64)
+    for f in range(nchan):
+        tab[:, f] = ramp[np.arange(ndm) % 16] + 3 * f + (np.arange(ndm) // 16)
+    nin = 2 * 1024 + 500 + int(tab.max())
+    nin += 1 - nin % 2
+    fil = rng.integers(0, 256, size=(nchan, nin)).astype(np.uint8)
+    check(fil, tab, "spread-%d" % spread)
+
+
 def test_dedispersed_pulse_found_by_search():
     # producer and consumer on the device: a dispersed pulse comes back at its
     # DM and time through sps_search, as the oracle finds it
