@@ -33,7 +33,10 @@ def run(fil, offset, in_place=False):
                                                 # limits, one 252-sample tile and its neighbours; over 1024
                                                 # channels the two-pass kernel
                                                 (65, 503, 10), (256, 252, 200), (257, 253, 0), (1024, 259, 64),
-                                                (1025, 300, 64), (16, 251, 3), (17, 505, 255)])
+                                                (1025, 300, 64), (16, 251, 3), (17, 505, 255),
+                                                # odd channel counts per wave and short rows of a tile or two
+                                                (33, 125, 7), (129, 123, 200), (513, 130, 1), (1023, 249, 64),
+                                                (48, 124, 9)])
 def test_zero_dm_parity(nchan, nsamp, offset):
     print("zero-dm case nchan=%d nsamp=%d offset=%d" % (nchan, nsamp, offset), flush=True)
     sys.stdout.flush()
