@@ -266,41 +266,68 @@ __global__ __launch_bounds__(256) void k_chan_stats(ChanMaskArgs a) {
   for (int b = tid; b < 4 * kCsCopies * kCsStride; b += 256) h[b] = 0;
   __syncthreads();
   uint32_t* mine = h + (wave * kCsCopies + (lane & (kCsCopies - 1))) * kCsStride;
-  // The row read as the aligned 4-byte words that cover it, whatever its
-  // alignment (rows of an odd length start anywhere in a word): bytes of a
-  // word outside the row are skipped. A word holding one byte of the row
-  // lies in the same page as that byte, so the reads stay in mapped memory.
+  // The row read as the aligned 16-byte chunks that cover it, whatever its
+  // alignment (rows of an odd length start anywhere), four chunks in flight
+  // per thread (enough bytes in flight to cover the memory latency); bytes
+  // of a chunk outside the row are skipped. A chunk holding one byte of the
+  // row lies in the same page as that byte, so the reads stay in mapped
+  // memory.
   const uintptr_t start = reinterpret_cast<uintptr_t>(a.in + (int64_t)f * a.nsamp);
-  const int lead = (int)(start & 3u);
-  const uint32_t* words = reinterpret_cast<const uint32_t*>(start - (uintptr_t)lead);
-  const int64_t last = lead + a.nsamp;  // one past the row's last byte, in word-byte units
+  const int lead = (int)(start & 15u);
+  const uint4* chunks = reinterpret_cast<const uint4*>(start - (uintptr_t)lead);
+  const int64_t last = lead + a.nsamp;  // one past the row's last byte, in chunk-byte units
   auto count4 = [&](uint32_t w) {
     atomicAdd(&mine[w & 0xFFu], 1u);
     atomicAdd(&mine[(w >> 8) & 0xFFu], 1u);
     atomicAdd(&mine[(w >> 16) & 0xFFu], 1u);
     atomicAdd(&mine[w >> 24], 1u);
   };
-  // words wholly inside the row: k = kf .. kl; four loads in flight per thread
-  const int64_t kf = lead > 0 ? 1 : 0, kl = (last >> 2) - 1;
+  auto count16 = [&](const uint4& c) {
+    count4(c.x);
+    count4(c.y);
+    count4(c.z);
+    count4(c.w);
+  };
+  // chunks wholly inside the row: k = kf .. kl, in steps of four chunks per
+  // thread; the next step's chunks are loaded while this step's are counted
+  // (a thread without a next step loads its current chunks again: every
+  // load is issued, none under a lane condition)
+  const int64_t kf = lead > 0 ? 1 : 0, kl = (last >> 4) - 1;
   int64_t k = kf + tid;
-  for (; k + 768 <= kl; k += 1024) {
-    const uint32_t w0 = words[k], w1 = words[k + 256], w2 = words[k + 512], w3 = words[k + 768];
-    count4(w0);
-    count4(w1);
-    count4(w2);
-    count4(w3);
+  if (k + 768 <= kl) {
+    uint4 c0 = chunks[k], c1 = chunks[k + 256], c2 = chunks[k + 512], c3 = chunks[k + 768];
+    while (true) {
+      const int64_t kn = k + 1024;
+      const bool more = kn + 768 <= kl;
+      const int64_t kq = more ? kn : k;
+      const uint4 n0 = chunks[kq], n1 = chunks[kq + 256], n2 = chunks[kq + 512], n3 = chunks[kq + 768];
+      count16(c0);
+      count16(c1);
+      count16(c2);
+      count16(c3);
+      k = kn;
+      if (!more) break;
+      c0 = n0;
+      c1 = n1;
+      c2 = n2;
+      c3 = n3;
+    }
   }
-  for (; k <= kl; k += 256) count4(words[k]);
-  // the words at the row's ends, byte by byte: only the row's bytes
+  for (; k <= kl; k += 256) {
+    const uint4 c = chunks[k];  // loaded whole before the atomics
+    count16(c);
+  }
+  // the chunks at the row's ends, byte by byte: only the row's bytes
   if (tid < 2) {
-    const int64_t ke = tid == 0 ? 0 : (last >> 2);
-    // (the last word is thread 1's unless it is word 0 and thread 0's already)
-    const bool edge = tid == 0 ? lead > 0 : ((last & 3) != 0 && (ke != 0 || lead == 0));
+    const int64_t ke = tid == 0 ? 0 : (last >> 4);
+    // (the last chunk is thread 1's unless it is chunk 0 and thread 0's already)
+    const bool edge = tid == 0 ? lead > 0 : ((last & 15) != 0 && (ke != 0 || lead == 0));
     if (edge) {
-      const uint32_t w = words[ke];
-      for (int q = 0; q < 4; ++q) {
-        const int64_t b = 4 * ke + q;
-        if (b >= lead && b < last) atomicAdd(&mine[(w >> (8 * q)) & 0xFFu], 1u);
+      const uint4 c = chunks[ke];
+      const uint32_t w4[4] = {c.x, c.y, c.z, c.w};
+      for (int q = 0; q < 16; ++q) {
+        const int64_t b = 16 * ke + q;
+        if (b >= lead && b < last) atomicAdd(&mine[(w4[q >> 2] >> (8 * (q & 3))) & 0xFFu], 1u);
       }
     }
   }
