@@ -8,17 +8,20 @@
 // rounded half up), is subtracted from every channel and the caller's offset
 // added, clamped to [0, 255]. Exact integer arithmetic.
 //
-// Design (gfx950, wave64): a workgroup covers 256 consecutive samples; lane
-// l of every wave owns samples 4l .. 4l+3 of that range (256 contiguous bytes
-// per wave and channel), and the 16 waves split the channels (wave w takes
-// f = w, w+16, ...), so many rows' loads are in flight at once. Rows of an
-// odd length start anywhere in a 4-byte word, so every access is made on
-// aligned words: a lane's 4 bytes are one or two aligned loads and a
-// v_alignbyte, and the rewrite stores whole aligned words, byte stores only
-// for the one or two words at the ends of a row's stretch. Partial sums meet
-// in LDS, one wave forms the levels, then each wave rewrites its own
-// channels. Traffic: the filterbank read twice (the second read mostly from
-// L2) and written once.
+// Design (gfx950, wave64). Zero-DM has two kernels. The read-once kernel
+// (k_zero_dm_reg, below) keeps each wave's channel words in registers from
+// the sums to the rewrite, so the filterbank is read once and written once;
+// it serves up to 1024 channels with input and output at one alignment mod
+// 4. The two-pass kernel (k_zero_dm) serves the rest: a workgroup covers
+// 256 consecutive samples; lane l of every wave owns samples 4l .. 4l+3 of
+// that range (256 contiguous bytes per wave and channel), and the 16 waves
+// split the channels (wave w takes f = w, w+16, ...), so many rows' loads
+// are in flight at once. Rows of an odd length start anywhere in a 4-byte
+// word, so every access is made on aligned words: a lane's 4 bytes are one
+// or two aligned loads and a v_alignbyte, and the rewrite stores whole
+// aligned words, byte stores only for the one or two words at the ends of a
+// row's stretch. Partial sums meet in LDS, one wave forms the levels, then
+// each wave re-reads and rewrites its own channels.
 #include <hip/hip_runtime.h>
 
 #include "sps_internal.h"
