@@ -423,16 +423,73 @@ __global__ __launch_bounds__(256) void k_chan_apply(ChanMaskArgs a) {
   }
 }
 
+// The same with 16-byte chunks, for input and output at one alignment mod
+// 16 (in place, or same-aligned buffers): chunk k of a row covers its bytes
+// 16 k - lead .. 16 k - lead + 15, aligned in both; four chunks per thread,
+// 256 apart, all loads before the stores (a lane's chunks are its own).
+// Whole chunks move as one load and one store; the one or two at the row's
+// ends byte by byte.
+__global__ __launch_bounds__(256) void k_chan_apply16(ChanMaskArgs a) {
+  for (int f = blockIdx.y; f < a.nchan; f += gridDim.y) {
+    const bool flag = a.stats[3 * (int64_t)f + 2] != 0;
+    if (!flag && a.in == a.out) continue;
+    const int64_t row = (int64_t)f * a.nsamp;
+    const int lead = (int)((reinterpret_cast<uintptr_t>(a.out + row)) & 15u);
+    const uint8_t mu = a.stats[3 * (int64_t)f];
+    const uint32_t fill = 0x01010101u * mu;
+    // whole chunks of the row: j = jf, jf + 16, ..., jl
+    const int64_t jf = (16 - lead) & 15, jl = jf + 16 * ((a.nsamp - 16 - jf) >> 4);
+    const uint4 fv = make_uint4(fill, fill, fill, fill);
+    const bool copy = !flag && jl >= jf;  // the row has whole chunks to copy
+    uint4 v[kApplyWords];
+    int64_t j[kApplyWords];
+#pragma unroll
+    for (int u = 0; u < kApplyWords; ++u)
+      j[u] = 16 * ((int64_t)blockIdx.x * (256 * kApplyWords) + u * 256 + threadIdx.x) - lead;
+    // every lane of a copied row loads (a whole chunk of the row, clamped;
+    // the others are not stored); a branch on the row's flag, the same for
+    // the whole workgroup
+    if (copy) {
+#pragma unroll
+      for (int u = 0; u < kApplyWords; ++u)
+        v[u] = *reinterpret_cast<const uint4*>(a.in + row + min(max(j[u], jf), jl));
+    } else {
+#pragma unroll
+      for (int u = 0; u < kApplyWords; ++u) v[u] = fv;
+    }
+#pragma unroll
+    for (int u = 0; u < kApplyWords; ++u)
+      if (j[u] >= 0 && j[u] + 16 <= a.nsamp) *reinterpret_cast<uint4*>(a.out + row + j[u]) = v[u];
+    // the chunks at the row's ends (no chunk value is needed here)
+#pragma unroll
+    for (int u = 0; u < kApplyWords; ++u) {
+      const int64_t j0 = j[u];
+      if (j0 < a.nsamp && j0 + 16 > 0 && !(j0 >= 0 && j0 + 16 <= a.nsamp)) {
+        for (int q = 0; q < 16; ++q) {
+          const int64_t jj = j0 + q;
+          if (jj >= 0 && jj < a.nsamp) a.out[row + jj] = flag ? mu : a.in[row + jj];
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_chan_mask(const ChanMaskArgs& a, hipStream_t s) {
   if (a.nsamp <= 0 || a.nchan <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_chan_stats, dim3((unsigned)a.nchan), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_chan_flags, dim3(1), dim3(256), 0, s, a);
-  // aligned output words of a row: at most nsamp / 4 + 2
-  const unsigned gx = (unsigned)((a.nsamp / 4 + 2 + 256 * kApplyWords - 1) / (256 * kApplyWords));
   const unsigned gy = (unsigned)min(a.nchan, 65535);
-  hipLaunchKernelGGL(k_chan_apply, dim3(gx, gy), dim3(256), 0, s, a);
+  if (((reinterpret_cast<uintptr_t>(a.in) ^ reinterpret_cast<uintptr_t>(a.out)) & 15u) == 0) {
+    // aligned 16-byte output chunks of a row: at most nsamp / 16 + 2
+    const unsigned gx = (unsigned)((a.nsamp / 16 + 2 + 256 * kApplyWords - 1) / (256 * kApplyWords));
+    hipLaunchKernelGGL(k_chan_apply16, dim3(gx, gy), dim3(256), 0, s, a);
+  } else {
+    // aligned output words of a row: at most nsamp / 4 + 2
+    const unsigned gx = (unsigned)((a.nsamp / 4 + 2 + 256 * kApplyWords - 1) / (256 * kApplyWords));
+    hipLaunchKernelGGL(k_chan_apply, dim3(gx, gy), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
