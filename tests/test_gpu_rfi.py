@@ -155,10 +155,11 @@ def test_chan_mask_then_zero_dm_full_size():
 
 @pytest.mark.parametrize("nchan,nsamp", [(13, 1001), (5, 4096), (3, 7), (40, 257)])
 def test_rfi_on_buffers_at_odd_byte_offsets(nchan, nsamp):
-    # inputs and outputs that start 1, 2 or 3 bytes into their buffer (every
+    # inputs and outputs that start 1 to 5 bytes into their buffer (every
     # row, the first included, starts inside a 4-byte word), in and out of
     # place; at the same alignment mod 4 zero-DM takes its read-once kernel,
-    # otherwise the two-pass one
+    # otherwise the two-pass one; the channel copy works in 16-byte chunks at
+    # the same alignment mod 16, otherwise in 4-byte words
     import torch
     m = sps()
     print("rfi odd offsets nchan=%d nsamp=%d" % (nchan, nsamp), flush=True)
@@ -177,7 +178,7 @@ def test_rfi_on_buffers_at_odd_byte_offsets(nchan, nsamp):
 
     zref = ro.zero_dm(fil, 40)
     mref, mu, sg, fl = ro.channel_mask(fil, 2)
-    for oi, oo in ((1, 3), (3, 1), (1, 0), (0, 3), (1, 1), (3, 3), (2, 2)):
+    for oi, oo in ((1, 3), (3, 1), (1, 0), (0, 3), (1, 1), (3, 3), (2, 2), (0, 4), (5, 1)):
         bi, xi = at(oi, fil)
         bo, xo = at(oo)
         m.zero_dm(xi, 40, out=xo)
